@@ -1,0 +1,182 @@
+/*
+ * libeg: minimum initial credits of energy games on AMD MI355X (gfx950).
+ *
+ * Problem (Formisano, Gentilini, Vella, arXiv 1710.03647, Sec. 3, Def. 4):
+ * given a total weighted arena (every vertex has an out-edge, Sec. 2) whose
+ * vertices are split between player 0 and player 1, compute for each vertex v
+ * whether player 0 wins from v and, if so, the least initial credit c(v) that
+ * keeps every prefix energy level non-negative (Eq. (1), Def. 3).
+ *
+ * Method: the least energy progress measure (Sec. 3.1, Def. 5) computed by
+ * repeated application of the lifting operator of Def. 6,
+ *     f(v) <- min (player 0) / max (player 1) over edges (v,u) of f(u) (-) w(v,u),
+ * where a (-) b = max(0, a - b) and TOP (-) b = TOP, starting from f = 0.  Values
+ * above the bound B become TOP; B = (n-1)*W by default, or M_G (Sec. 3.1).  The
+ * device iteration follows the frontier scheme of Alg. 3: each round lifts the
+ * active vertices in parallel, in place, and the predecessors of every vertex
+ * whose value changed form the next active set.  All arithmetic is integer, so
+ * the result equals the sequential worklist of Alg. 1 bit for bit.
+ *
+ * Output: credits[v] = c(v) for v won by player 0, EG_TOP for v won by player 1.
+ *
+ * Conventions for every function:
+ *  - return EG_OK (0) on success, a negative EG_E* code on failure; nothing
+ *    throws across this boundary;
+ *  - on failure eg_last_error() returns a message for the calling thread;
+ *  - every input array is copied before the call returns (the caller keeps
+ *    ownership); output arrays are caller-owned and written in full on EG_OK
+ *    (and on EG_ETIMEDOUT, see eg_solve).
+ */
+#ifndef EG_H
+#define EG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EG_TOP INT64_MAX /* credit of a vertex won by player 1 (TOP); keeps the order of Sec. 3.1 */
+
+enum {
+  EG_OK = 0,
+  EG_PENDING = 1,     /* eg_poll: the game is not finished yet */
+  EG_EINVAL = -1,     /* malformed arguments or arena (see eg_check) */
+  EG_ENOMEM = -2,     /* device memory or the context's HBM budget cannot hold the game */
+  EG_EDEVICE = -3,    /* a HIP call failed */
+  EG_ETIMEDOUT = -4,  /* the round or time budget ran out; credits hold a lower bound */
+  EG_EBUSY = -5,      /* eg_submit: the pending queue is full */
+  EG_ENOTFOUND = -6,  /* unknown or already retired ticket */
+  EG_ECANCELED = -7   /* the ticket was cancelled, or its context destroyed */
+};
+
+enum { EG_BOUND_NW = 0, /* B = (n-1)*W */ EG_BOUND_MG = 1 /* B = M_G of Sec. 3.1 */ };
+enum { EG_MEM_HOST = 0, EG_MEM_DEVICE = 1 };
+
+typedef struct eg_ctx eg_ctx;
+typedef struct eg_game eg_game;
+typedef uint64_t eg_ticket;
+
+/* Context configuration.  Zero-initialise and set what is needed. */
+typedef struct {
+  int device;                /* HIP device ordinal */
+  void* hip_stream;          /* hipStream_t used by eg_create/eg_solve; NULL = the context's own */
+  uint64_t hbm_budget_bytes; /* serving: device bytes the admitted games may hold; 0 = 80% of free */
+  int max_slots;             /* serving: games resident at once; 0 = 1024 */
+  int bound_mode;            /* EG_BOUND_NW or EG_BOUND_MG */
+  uint64_t max_rounds;       /* eg_solve round budget; 0 = none */
+  double time_budget_s;      /* eg_solve wall-clock budget; 0 = none */
+  int max_pending;           /* serving: queue cap of eg_submit; 0 = 65536 */
+} eg_config;
+
+/* A game in CSR form.  Out-edges of v are e in [offsets[v], offsets[v+1]),
+ * going to targets[e] with weight weights[e] (a multiset: duplicate edges and
+ * self-loops are allowed).  owner_bits is LSB-first, bit v = 1 when v belongs
+ * to player 1 (max).  W must satisfy W >= max(0, max_e -weights[e]).
+ * mem = EG_MEM_HOST: host pointers.  mem = EG_MEM_DEVICE: device pointers valid
+ * on the context's stream until the call returns. */
+typedef struct {
+  int32_t n;
+  int64_t m;
+  const int64_t* offsets;    /* n+1 entries, offsets[0] = 0, offsets[n] = m, non-decreasing */
+  const int32_t* targets;    /* m entries in [0, n) */
+  const int32_t* weights;    /* m entries */
+  const uint8_t* owner_bits; /* ceil(n/8) bytes */
+  int32_t W;
+  int mem;
+} eg_game_desc;
+
+/* Counters and times of one solve. */
+typedef struct {
+  uint64_t rounds;        /* rounds of the frontier iteration that had a non-empty active set */
+  uint64_t lifts;         /* applications of the lifting operator */
+  uint64_t relaxed_edges; /* out-edges read by those lifts (GTEPS = relaxed_edges / t_solve) */
+  uint64_t pushes;        /* insertions into the next active set */
+  uint64_t changes;       /* lifts that raised a value */
+  double t_upload;        /* eg_create: host-to-device copy and layout, seconds */
+  double t_rcsr;          /* eg_create: reverse CSR (predecessor lists) build, seconds */
+  double t_solve;         /* eg_solve: from the init launch to the fixpoint, seconds */
+  double t_d2h;           /* eg_solve: result conversion and device-to-host copy, seconds */
+  double model_bytes;     /* algorithmic bytes moved by the solve (see DESIGN) */
+  double achieved_gbps;   /* model_bytes / t_solve / 1e9 */
+} eg_stats;
+
+/* What eg_check derives from a valid game. */
+typedef struct {
+  int32_t n;
+  int64_t m;
+  int64_t bound;           /* B */
+  int value_bits;          /* 32 or 64: device storage of f */
+  uint64_t device_bytes;   /* device footprint of the game */
+  int32_t max_outdeg;
+  int32_t max_indeg;
+} eg_game_info;
+
+/* Per-call options of eg_solve_ex. */
+typedef struct {
+  uint64_t max_rounds;    /* 0 = the context's budget */
+  double time_budget_s;   /* 0 = the context's budget */
+  int resume;             /* 0: start from f = 0 with the initial active set of Alg. 3.
+                             1: start from the game's current f with every vertex active
+                                (any f below the least fixpoint reaches it). */
+  int driver;             /* 0 = automatic; see eg_solve_ex */
+} eg_solve_opts;
+
+/* Create a context on cfg->device (NULL cfg = all defaults).  Returns EG_EDEVICE
+ * when HIP cannot use the device. */
+int eg_ctx_create(const eg_config* cfg, eg_ctx** out);
+
+/* Destroy a context: stops its serving thread, fails in-flight tickets with
+ * EG_ECANCELED, frees every game still alive in it. */
+int eg_ctx_destroy(eg_ctx* ctx);
+
+/* Validate a game without touching a device (host pointers only).  EG_EINVAL
+ * when: n < 1; m < 0 or m >= 2^31; offsets not starting at 0, not ending at m,
+ * or decreasing; a target outside [0, n); a vertex without out-edges (the arena
+ * is not total, Sec. 2); W < max(0, max -w); a null pointer.  info may be NULL. */
+int eg_check(const eg_game_desc* desc, int bound_mode, eg_game_info* info, char* msg, size_t msg_len);
+
+/* Validate (as eg_check), copy the game to the device, lay it out and build
+ * its predecessor lists (the paper's CSC, Sec. 5).  Synchronises the context's
+ * stream.  stats (nullable) receives t_upload and t_rcsr. */
+int eg_create(eg_ctx* ctx, const eg_game_desc* desc, eg_game** out, eg_stats* stats);
+
+/* Free a game's device memory. */
+int eg_destroy(eg_game* g);
+
+/* Solve one game to the least fixpoint and copy credits (n entries,
+ * caller-owned host memory; NULL = keep the result on the device only).
+ * Blocks until done.  EG_ETIMEDOUT when a budget ran out: credits then hold the
+ * current measure, a lower bound of the least one (TOP only where proven).
+ * stats is nullable.  Calls on one context are serialised. */
+int eg_solve(eg_game* g, int64_t* credits, eg_stats* stats);
+
+/* eg_solve with per-call options (NULL opts = eg_solve). */
+int eg_solve_ex(eg_game* g, const eg_solve_opts* opts, int64_t* credits, eg_stats* stats);
+
+/* Replace the game's current measure (n entries, host memory, EG_TOP allowed)
+ * before an eg_solve_ex with resume = 1.  EG_EINVAL if a finite value is
+ * negative or above the bound. */
+int eg_set_measure(eg_game* g, const int64_t* f);
+
+/* Serving.  eg_submit copies the game into the context's pending queue and
+ * returns at once with a ticket (EG_EBUSY if the queue is full, EG_EINVAL for
+ * a malformed game, EG_ENOMEM if the game cannot fit even an empty budget).
+ * A serving thread admits pending games while their device footprint fits the
+ * HBM budget and a slot is free, and runs all admitted games together in one
+ * batched device iteration; a game that arrives while others run joins them at
+ * the next round.  eg_poll returns EG_OK with the credits (n entries) once the
+ * game is done (the ticket is then retired), EG_PENDING before, or the
+ * ticket's error.  eg_cancel drops a pending or running ticket. */
+int eg_submit(eg_ctx* ctx, const eg_game_desc* desc, eg_ticket* out);
+int eg_poll(eg_ctx* ctx, eg_ticket t, int64_t* credits, eg_stats* stats);
+int eg_cancel(eg_ctx* ctx, eg_ticket t);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char* eg_last_error(eg_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EG_H */

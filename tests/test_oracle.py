@@ -1,0 +1,113 @@
+"""The CPU oracle against its pins (no GPU).
+
+Sources of truth: brute force over positional strategies (Lemma 1), closed
+forms, the fixpoint condition of Def. 6 evaluated with numpy, and invariants
+that follow from the least-fixpoint characterisation in Sec. 3.1.
+"""
+import numpy as np
+import pytest
+
+import pins
+from paper_1710_03647_amd import synth
+
+TOP = pins.TOP
+
+
+@pytest.fixture(scope="module")
+def solve(oracle_mod):
+    return lambda g, **kw: oracle_mod.solve(g, **kw).f
+
+
+@pytest.mark.parametrize("owner_mode", ["mixed", "p0", "p1"])
+def test_brute_force_fw(solve, owner_mode):
+    pins.pin_brute(solve, count=4000, n_max=7, deg_max=3, wlim=4, owner_mode=owner_mode,
+                   seed0={"mixed": 10_000, "p0": 20_000, "p1": 30_000}[owner_mode])
+
+
+def test_brute_force_dfs(solve):
+    pins.pin_brute(solve, count=1500, n_max=6, deg_max=3, wlim=5, seed0=40_000, checker="dfs")
+
+
+def test_brute_checkers_agree():
+    """The two brute-force evaluations agree with each other."""
+    from oracle import brute
+
+    for s in range(400):
+        g = synth.gen_random_small(50_000 + s, n_max=6, deg_max=3, wlim=4)
+        pins.expect_equal(brute.credits_dfs(g), brute.credits_fw(g), f"seed {s}")
+
+
+@pytest.mark.parametrize("pin", pins.CLOSED_FORMS, ids=lambda p: p.__name__)
+def test_closed_form(solve, pin):
+    pin(solve)
+
+
+def test_cf8_lift_count(oracle_mod):
+    """The -1 self-loop climbs through every value 0..B before TOP: B+1 changes and
+    B+2 lifts (the last lift confirms TOP).  Pins the cap at strictly above B."""
+    for k in (1, 7, 100):
+        r = oracle_mod.solve(pins.cf8_game(k))
+        assert r.bound == k
+        assert r.changes == k + 1
+        assert r.lifts == k + 2
+
+
+@pytest.mark.parametrize("order", ["fifo", "lifo", "random", "jacobi", "rounds", "alg1"])
+def test_every_order_matches_brute_force(oracle_mod, order):
+    pins.pin_brute(lambda g: oracle_mod.solve(g, order=order).f, count=600, seed0=60_000)
+
+
+@pytest.mark.parametrize("gi", range(5))
+def test_invariants_medium(oracle_mod, gi):
+    g = pins.medium_games()[gi]
+    base = oracle_mod.solve(g)
+    B = base.bound
+    assert B == (g.n - 1) * g.W
+    f = base.f
+    # the games exercise both finite credits and TOP
+    assert (f == TOP).any() and (f[f != TOP] > 0).any()
+    # I1/I2: fixpoint of Def. 6 within the codomain
+    pins.pin_fixpoint(g, f, B, g.name)
+    assert oracle_mod.count_unstable(g, f, B) == 0
+    # I4: iteration order does not change the least fixpoint
+    for order in ("lifo", "random", "jacobi", "rounds", "alg1"):
+        pins.expect_equal(oracle_mod.solve(g, order=order).f, f, f"I4 {order}")
+    # I3: any bound at least the largest finite credit gives the same result
+    pins.expect_equal(oracle_mod.solve(g, bound_mode=1).f, f, "I3 M_G")
+    pins.expect_equal(oracle_mod.solve(g, bound_mode=2, bound=2 * B).f, f, "I3 2B")
+    # I5: relabelling vertex ids permutes the result
+    perm = np.argsort(synth.draws(99, 5, 0, g.n), kind="stable")  # old v -> new perm[v]
+    src = np.repeat(np.arange(g.n), np.diff(g.off))
+    gp = synth.from_edges(g.n, perm[src], perm[g.tgt], g.w, np.empty(g.n, np.uint8), W=g.W)
+    gp.owner[perm] = g.owner
+    fp = oracle_mod.solve(gp).f
+    pins.expect_equal(fp[perm], f, "I5 relabel")
+    # I6: raising every weight never raises a credit
+    gh = synth.Game(g.n, g.off, g.tgt, (g.w.astype(np.int64) + 3).astype(np.int32), g.owner, W=g.W)
+    fh = oracle_mod.solve(gh).f
+    assert np.all(fh <= f), "I6 monotone in the weights"
+    # I8: stop early, then resume from the partial measure with every vertex queued
+    part = oracle_mod.solve(g, max_lifts=max(1, base.lifts // 3))
+    assert part.status == 1 and np.all(part.f <= f)
+    pins.expect_equal(oracle_mod.solve(g, f_init=part.f).f, f, "I8 resume")
+    # I8: resume from any measure below the least fixpoint
+    noise = synth.to_int(synth.draws(7, 2, 0, g.n), 0, 3 * g.W)
+    f0 = np.minimum(f, noise)
+    pins.expect_equal(oracle_mod.solve(g, f_init=f0).f, f, "I8 from below")
+
+
+def test_fixpoint_is_not_sufficient(oracle_mod):
+    """A 0-weight 2-cycle of player-0 vertices set to TOP is a fixpoint but not the
+    least one: the oracle must give 0 there."""
+    g = synth.make_game(2, [(0, 1, 0), (1, 0, 0)], [0, 0], W=0)
+    fake = np.array([TOP, TOP], dtype=np.int64)
+    pins.pin_fixpoint(g, fake, 1)
+    pins.expect_equal(oracle_mod.solve(g).f, [0, 0], "least")
+
+
+def test_plain_config_summary(oracle_mod):
+    """Plain config: n=1000, out-degree 4, weights in [-10, 10], seed 1."""
+    g = synth.gen_plain()
+    r = oracle_mod.solve(g)
+    assert r.status == 0 and r.bound == 9990
+    pins.pin_fixpoint(g, r.f, r.bound, "plain")
