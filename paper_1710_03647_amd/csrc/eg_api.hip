@@ -1,0 +1,457 @@
+// libeg host runtime and C-ABI: validation, device layout, the round driver
+// of the frontier iteration (Alg. 3), result conversion and statistics.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "eg.h"
+#include "eg_internal.h"
+#include "eg_serve.h"
+
+namespace {
+
+thread_local std::string t_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  t_err = buf;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess) return fail(EG_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+namespace eg {
+
+void set_error(const char* msg) { t_err = msg; }
+const char* get_error() { return t_err.c_str(); }
+
+// Host-side validation of a game (host pointers).  Fills info; 0 or EG_EINVAL.
+int check_host(const eg_game_desc* d, int bound_mode, eg_game_info* info, std::string* why) {
+  auto bad = [&](const char* fmt, auto... a) {
+    char buf[256];
+    snprintf(buf, sizeof buf, fmt, a...);
+    *why = buf;
+    return EG_EINVAL;
+  };
+  if (!d) return bad("null game descriptor");
+  if (d->n < 1) return bad("n = %d: a game needs at least one vertex", d->n);
+  if (d->m < 0 || d->m >= ((int64_t)1 << 31)) return bad("m = %lld outside [0, 2^31)", (long long)d->m);
+  if (!d->offsets || !d->owner_bits) return bad("null offsets or owner_bits");
+  if (d->m > 0 && (!d->targets || !d->weights)) return bad("null targets or weights");
+  if (d->W < 0) return bad("W = %d is negative", d->W);
+  if (bound_mode != EG_BOUND_NW && bound_mode != EG_BOUND_MG) return bad("unknown bound mode %d", bound_mode);
+  const int32_t n = d->n;
+  const int64_t* off = d->offsets;
+  if (off[0] != 0) return bad("offsets[0] = %lld, must be 0", (long long)off[0]);
+  if (off[n] != d->m) return bad("offsets[n] = %lld, must equal m = %lld", (long long)off[n], (long long)d->m);
+  int32_t max_out = 0;
+  int64_t mg = 0;
+  int32_t most_negative = 0;
+  for (int32_t v = 0; v < n; v++) {
+    const int64_t a = off[v], b = off[v + 1];
+    if (b < a) return bad("offsets decrease at vertex %d", v);
+    if (b == a) return bad("vertex %d has no out-edge: the arena is not total", v);
+    max_out = std::max<int32_t>(max_out, (int32_t)std::min<int64_t>(b - a, INT32_MAX));
+    int32_t worst = 0;
+    for (int64_t e = a; e < b; e++) {
+      const int32_t t = d->targets[e];
+      if (t < 0 || t >= n) return bad("edge %lld of vertex %d targets %d, outside [0, %d)", (long long)e, v, t, n);
+      const int32_t w = d->weights[e];
+      if (w < 0 && -(int64_t)w > worst) worst = (int32_t)std::min<int64_t>(-(int64_t)w, INT32_MAX);
+    }
+    mg += worst;
+    most_negative = std::max(most_negative, worst);
+  }
+  if ((int64_t)d->W < most_negative)
+    return bad("W = %d is below the largest negative weight magnitude %d", d->W, most_negative);
+  const int64_t bound = bound_mode == EG_BOUND_MG ? mg : (int64_t)(n - 1) * (int64_t)d->W;
+  // TOP is encoded as B + W + 1 and a term reaches at most B + 2W + 1
+  const __int128 hi = (__int128)bound + 2 * (__int128)d->W + 1;
+  if (hi > (__int128)INT64_MAX) return bad("bound %lld + 2W + 1 overflows int64", (long long)bound);
+  std::vector<int32_t> indeg(n, 0);
+  int32_t max_in = 0;
+  for (int64_t e = 0; e < d->m; e++) max_in = std::max(max_in, ++indeg[d->targets[e]]);
+  if (info) {
+    info->n = n;
+    info->m = d->m;
+    info->bound = bound;
+    info->value_bits = hi < ((__int128)1 << 31) ? 32 : 64;
+    info->max_outdeg = max_out;
+    info->max_indeg = max_in;
+    const size_t vb = info->value_bits / 8;
+    const size_t nn = (size_t)n, mm = (size_t)d->m;
+    info->device_bytes = align_up(4 * (nn + 1)) + align_up(8 * mm) + align_up(4 * (nn + 1)) +
+                         align_up(4 * mm) + align_up(vb * nn) + 3 * align_up(4 * nn) +
+                         align_up(8 * nn) + 2 * 256;
+  }
+  return EG_OK;
+}
+
+}  // namespace eg
+
+struct eg_ctx {
+  eg_config cfg;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int grid = 2048;
+  std::mutex solve_mu;
+  eg::Server* server = nullptr;
+};
+
+struct eg_game {
+  eg_ctx* ctx = nullptr;
+  int32_t n = 0;
+  int64_t m = 0;
+  int32_t W = 0;
+  int64_t bound = 0;
+  int vbits = 64;
+  int h = 1;
+  eg_game_info info{};
+  void* arena = nullptr;
+  eg::DevGame dg{};
+  int64_t* out64 = nullptr;
+  uint32_t* h_ctrl = nullptr;
+  unsigned long long* h_stats = nullptr;
+  hipEvent_t ev[4] = {};
+};
+
+extern "C" {
+
+const char* eg_last_error(eg_ctx*) { return t_err.c_str(); }
+
+int eg_check(const eg_game_desc* desc, int bound_mode, eg_game_info* info, char* msg, size_t msg_len) {
+  std::string why;
+  if (desc && desc->mem != EG_MEM_HOST) {
+    why = "eg_check takes host pointers only";
+    if (msg && msg_len) snprintf(msg, msg_len, "%s", why.c_str());
+    return fail(EG_EINVAL, "%s", why.c_str());
+  }
+  int rc = eg::check_host(desc, bound_mode, info, &why);
+  if (msg && msg_len) snprintf(msg, msg_len, "%s", why.c_str());
+  if (rc != EG_OK) return fail(rc, "%s", why.c_str());
+  return EG_OK;
+}
+
+int eg_ctx_create(const eg_config* cfg, eg_ctx** out) {
+  if (!out) return fail(EG_EINVAL, "null output pointer");
+  *out = nullptr;
+  eg_config c{};
+  if (cfg) c = *cfg;
+  if (c.bound_mode != EG_BOUND_NW && c.bound_mode != EG_BOUND_MG)
+    return fail(EG_EINVAL, "unknown bound mode %d", c.bound_mode);
+  int ndev = 0;
+  HIPCHK(hipGetDeviceCount(&ndev));
+  if (c.device < 0 || c.device >= ndev) return fail(EG_EDEVICE, "device %d not present (%d devices)", c.device, ndev);
+  HIPCHK(hipSetDevice(c.device));
+  eg_ctx* ctx = new eg_ctx();
+  ctx->cfg = c;
+  if (c.hip_stream) {
+    ctx->stream = (hipStream_t)c.hip_stream;
+  } else {
+    hipError_t e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      delete ctx;
+      return fail(EG_EDEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
+    }
+    ctx->own_stream = true;
+  }
+  ctx->grid = eg::round_grid(c.device);
+  *out = ctx;
+  return EG_OK;
+}
+
+int eg_ctx_destroy(eg_ctx* ctx) {
+  if (!ctx) return fail(EG_EINVAL, "null context");
+  hipSetDevice(ctx->cfg.device);
+  if (ctx->server) {
+    eg::server_destroy(ctx->server);
+    ctx->server = nullptr;
+  }
+  if (ctx->own_stream) hipStreamDestroy(ctx->stream);
+  delete ctx;
+  return EG_OK;
+}
+
+static void game_free(eg_game* g) {
+  if (!g) return;
+  if (g->arena) hipFree(g->arena);
+  if (g->h_ctrl) hipHostFree(g->h_ctrl);
+  if (g->h_stats) hipHostFree(g->h_stats);
+  for (auto& e : g->ev)
+    if (e) hipEventDestroy(e);
+  delete g;
+}
+
+int eg_create(eg_ctx* ctx, const eg_game_desc* desc, eg_game** out, eg_stats* st) {
+  if (!ctx || !desc || !out) return fail(EG_EINVAL, "null argument");
+  *out = nullptr;
+  HIPCHK(hipSetDevice(ctx->cfg.device));
+  hipStream_t s = ctx->stream;
+  // host view of the inputs for validation
+  eg_game_desc hd = *desc;
+  std::vector<int64_t> hoff;
+  std::vector<int32_t> htgt, hw;
+  std::vector<uint8_t> hown;
+  if (desc->mem == EG_MEM_DEVICE) {
+    if (desc->n < 1 || desc->m < 0) return fail(EG_EINVAL, "n = %d, m = %lld", desc->n, (long long)desc->m);
+    if (!desc->offsets || !desc->owner_bits || (desc->m > 0 && (!desc->targets || !desc->weights)))
+      return fail(EG_EINVAL, "null device pointer");
+    hoff.resize((size_t)desc->n + 1);
+    htgt.resize((size_t)desc->m);
+    hw.resize((size_t)desc->m);
+    hown.resize(((size_t)desc->n + 7) / 8);
+    HIPCHK(hipMemcpyAsync(hoff.data(), desc->offsets, 8 * hoff.size(), hipMemcpyDeviceToHost, s));
+    if (desc->m > 0) {
+      HIPCHK(hipMemcpyAsync(htgt.data(), desc->targets, 4 * htgt.size(), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(hw.data(), desc->weights, 4 * hw.size(), hipMemcpyDeviceToHost, s));
+    }
+    HIPCHK(hipMemcpyAsync(hown.data(), desc->owner_bits, hown.size(), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    hd.offsets = hoff.data();
+    hd.targets = htgt.data();
+    hd.weights = hw.data();
+    hd.owner_bits = hown.data();
+    hd.mem = EG_MEM_HOST;
+  } else if (desc->mem != EG_MEM_HOST) {
+    return fail(EG_EINVAL, "unknown memory kind %d", desc->mem);
+  }
+  eg_game_info info{};
+  std::string why;
+  if (eg::check_host(&hd, ctx->cfg.bound_mode, &info, &why) != EG_OK) return fail(EG_EINVAL, "%s", why.c_str());
+
+  eg_game* g = new eg_game();
+  g->ctx = ctx;
+  g->n = desc->n;
+  g->m = desc->m;
+  g->W = desc->W;
+  g->bound = info.bound;
+  g->vbits = info.value_bits;
+  g->info = info;
+  g->h = eg::pick_h((double)desc->m / desc->n);
+  const size_t nn = (size_t)g->n, mm = (size_t)g->m, vb = g->vbits / 8;
+  // one device allocation holds everything the game keeps
+  size_t offs[11], total = 0;
+  const size_t sizes[11] = {4 * (nn + 1), 8 * mm, 4 * (nn + 1), 4 * mm, vb * nn, 4 * nn, 4 * nn, 4 * nn,
+                            8 * nn, 4 * eg::C_WORDS, 8 * eg::S_WORDS};
+  for (int i = 0; i < 11; i++) {
+    offs[i] = total;
+    total += align_up(std::max<size_t>(sizes[i], 4));
+  }
+  hipError_t e = hipMalloc(&g->arena, total);
+  if (e != hipSuccess) {
+    game_free(g);
+    return fail(EG_ENOMEM, "device allocation of %zu bytes failed: %s", total, hipGetErrorString(e));
+  }
+  char* base = (char*)g->arena;
+  eg::DevGame& dg = g->dg;
+  dg.n = g->n;
+  dg.m = (uint32_t)g->m;
+  dg.rs = (uint32_t*)(base + offs[0]);
+  dg.edges = (int2*)(base + offs[1]);
+  dg.rev_off = (uint32_t*)(base + offs[2]);
+  dg.rev_src = (int32_t*)(base + offs[3]);
+  dg.f = base + offs[4];
+  dg.stamp = (uint32_t*)(base + offs[5]);
+  dg.wl0 = (int32_t*)(base + offs[6]);
+  dg.wl1 = (int32_t*)(base + offs[7]);
+  g->out64 = (int64_t*)(base + offs[8]);
+  dg.ctrl = (uint32_t*)(base + offs[9]);
+  dg.stats = (unsigned long long*)(base + offs[10]);
+  dg.bound = g->bound;
+  dg.top = g->bound + g->W + 1;
+
+  auto cleanup_fail = [&](int code, const char* what, hipError_t err) {
+    game_free(g);
+    return fail(code, "%s: %s", what, hipGetErrorString(err));
+  };
+  if ((e = hipHostMalloc((void**)&g->h_ctrl, 4 * eg::C_WORDS, hipHostMallocDefault)) != hipSuccess)
+    return cleanup_fail(EG_EDEVICE, "hipHostMalloc", e);
+  if ((e = hipHostMalloc((void**)&g->h_stats, 8 * eg::S_WORDS, hipHostMallocDefault)) != hipSuccess)
+    return cleanup_fail(EG_EDEVICE, "hipHostMalloc", e);
+  for (auto& ev : g->ev)
+    if ((e = hipEventCreate(&ev)) != hipSuccess) return cleanup_fail(EG_EDEVICE, "hipEventCreate", e);
+
+  // staging for the raw inputs (host path) plus reverse-CSR scratch
+  const size_t scan_words = eg::scan_tmp_words(nn + 1);
+  const bool host_in = desc->mem == EG_MEM_HOST;
+  size_t so[6], stotal = 0;
+  const size_t ssz[6] = {host_in ? 8 * (nn + 1) : 0, host_in ? 4 * mm : 0, host_in ? 4 * mm : 0,
+                         host_in ? (nn + 7) / 8 : 0, 4 * (nn + 1), 4 * scan_words};
+  for (int i = 0; i < 6; i++) {
+    so[i] = stotal;
+    stotal += align_up(std::max<size_t>(ssz[i], 4));
+  }
+  void* staging = nullptr;
+  if ((e = hipMalloc(&staging, stotal)) != hipSuccess) return cleanup_fail(EG_ENOMEM, "staging allocation", e);
+  char* sb = (char*)staging;
+  const int64_t* d_off = host_in ? (const int64_t*)(sb + so[0]) : desc->offsets;
+  const int32_t* d_tgt = host_in ? (const int32_t*)(sb + so[1]) : desc->targets;
+  const int32_t* d_w = host_in ? (const int32_t*)(sb + so[2]) : desc->weights;
+  const uint8_t* d_own = host_in ? (const uint8_t*)(sb + so[3]) : desc->owner_bits;
+  uint32_t* cursor = (uint32_t*)(sb + so[4]);
+  uint32_t* scan_tmp = (uint32_t*)(sb + so[5]);
+
+  auto run = [&]() -> hipError_t {
+    hipError_t r;
+    if ((r = hipEventRecord(g->ev[0], s)) != hipSuccess) return r;
+    if (host_in) {
+      if ((r = hipMemcpyAsync((void*)d_off, desc->offsets, 8 * (nn + 1), hipMemcpyHostToDevice, s))) return r;
+      if (mm && (r = hipMemcpyAsync((void*)d_tgt, desc->targets, 4 * mm, hipMemcpyHostToDevice, s))) return r;
+      if (mm && (r = hipMemcpyAsync((void*)d_w, desc->weights, 4 * mm, hipMemcpyHostToDevice, s))) return r;
+      if ((r = hipMemcpyAsync((void*)d_own, desc->owner_bits, (nn + 7) / 8, hipMemcpyHostToDevice, s))) return r;
+    }
+    if ((r = eg::launch_layout(d_off, d_own, d_tgt, d_w, g->n, (uint32_t)mm, (uint32_t*)dg.rs,
+                               (int2*)dg.edges, s)) != hipSuccess) return r;
+    if ((r = hipEventRecord(g->ev[1], s)) != hipSuccess) return r;
+    if ((r = eg::launch_reverse_csr(dg.rs, dg.edges, g->n, (uint32_t)mm, (uint32_t*)dg.rev_off,
+                                    (int32_t*)dg.rev_src, cursor, scan_tmp, scan_words, s)) != hipSuccess)
+      return r;
+    if ((r = hipEventRecord(g->ev[2], s)) != hipSuccess) return r;
+    return hipStreamSynchronize(s);
+  };
+  e = run();
+  hipFree(staging);
+  if (e != hipSuccess) return cleanup_fail(EG_EDEVICE, "upload/layout/reverse CSR", e);
+  if (st) {
+    memset(st, 0, sizeof *st);
+    float ms = 0;
+    hipEventElapsedTime(&ms, g->ev[0], g->ev[1]);
+    st->t_upload = ms * 1e-3;
+    hipEventElapsedTime(&ms, g->ev[1], g->ev[2]);
+    st->t_rcsr = ms * 1e-3;
+  }
+  *out = g;
+  return EG_OK;
+}
+
+int eg_destroy(eg_game* g) {
+  if (!g) return fail(EG_EINVAL, "null game");
+  hipSetDevice(g->ctx->cfg.device);
+  game_free(g);
+  return EG_OK;
+}
+
+int eg_set_measure(eg_game* g, const int64_t* f) {
+  if (!g || !f) return fail(EG_EINVAL, "null argument");
+  for (int32_t v = 0; v < g->n; v++)
+    if (f[v] != EG_TOP && (f[v] < 0 || f[v] > g->bound))
+      return fail(EG_EINVAL, "f[%d] = %lld outside [0, %lld] and not EG_TOP", v, (long long)f[v], (long long)g->bound);
+  std::lock_guard<std::mutex> lock(g->ctx->solve_mu);
+  HIPCHK(hipSetDevice(g->ctx->cfg.device));
+  hipStream_t s = g->ctx->stream;
+  HIPCHK(hipMemcpyAsync(g->out64, f, 8 * (size_t)g->n, hipMemcpyHostToDevice, s));
+  HIPCHK(eg::launch_input(g->dg, g->vbits, g->out64, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return EG_OK;
+}
+
+int eg_solve_ex(eg_game* g, const eg_solve_opts* opts, int64_t* credits, eg_stats* st) {
+  if (!g) return fail(EG_EINVAL, "null game");
+  eg_solve_opts o{};
+  if (opts) o = *opts;
+  eg_ctx* ctx = g->ctx;
+  const uint64_t max_rounds = o.max_rounds ? o.max_rounds : ctx->cfg.max_rounds;
+  const double budget = o.time_budget_s > 0 ? o.time_budget_s : ctx->cfg.time_budget_s;
+  std::lock_guard<std::mutex> lock(ctx->solve_mu);
+  HIPCHK(hipSetDevice(ctx->cfg.device));
+  hipStream_t s = ctx->stream;
+  const eg::DevGame& dg = g->dg;
+  const double t0 = now_s();
+  HIPCHK(hipMemsetAsync(dg.ctrl, 0, 4 * eg::C_WORDS, s));
+  HIPCHK(hipMemsetAsync(dg.stats, 0, 8 * eg::S_WORDS, s));
+  HIPCHK(hipEventRecord(g->ev[0], s));
+  HIPCHK(eg::launch_init(dg, g->vbits, g->h, o.resume ? 1 : 0, s));
+  uint32_t r = 1;
+  uint64_t launched = 0;
+  uint32_t batch = 2;
+  int status = EG_OK;
+  for (;;) {
+    uint32_t k = batch;
+    if (max_rounds && launched + k > max_rounds) k = (uint32_t)(max_rounds - launched);
+    for (uint32_t j = 0; j < k; j++) HIPCHK(eg::launch_round(dg, g->vbits, g->h, r++, ctx->grid, s));
+    launched += k;
+    HIPCHK(hipMemcpyAsync(g->h_ctrl, dg.ctrl, 4 * eg::C_WORDS, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (g->h_ctrl[eg::C_CNT0 + r % 3] == 0) break;  // empty active set: fixpoint
+    if ((max_rounds && launched >= max_rounds) || (budget > 0 && now_s() - t0 > budget) ||
+        r > 0xFFFFFF00u) {
+      status = EG_ETIMEDOUT;
+      break;
+    }
+    if (batch < 64) batch *= 2;
+  }
+  HIPCHK(hipEventRecord(g->ev[1], s));
+  HIPCHK(hipMemcpyAsync(g->h_stats, dg.stats, 8 * eg::S_WORDS, hipMemcpyDeviceToHost, s));
+  if (credits) {
+    HIPCHK(eg::launch_output(dg, g->vbits, g->out64, s));
+    HIPCHK(hipMemcpyAsync(credits, g->out64, 8 * (size_t)g->n, hipMemcpyDeviceToHost, s));
+  }
+  HIPCHK(hipEventRecord(g->ev[2], s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (st) {
+    memset(st, 0, sizeof *st);
+    st->rounds = g->h_ctrl[eg::C_ROUNDS];
+    st->lifts = g->h_stats[eg::S_LIFTS];
+    st->relaxed_edges = g->h_stats[eg::S_EDGES];
+    st->pushes = g->h_stats[eg::S_PUSHES];
+    st->changes = g->h_stats[eg::S_CHANGES];
+    float ms = 0;
+    hipEventElapsedTime(&ms, g->ev[0], g->ev[1]);
+    st->t_solve = ms * 1e-3;
+    hipEventElapsedTime(&ms, g->ev[1], g->ev[2]);
+    st->t_d2h = ms * 1e-3;
+    const double vb = g->vbits / 8;
+    // algorithmic bytes: per relaxed edge the {target, weight} pair and f(target);
+    // per lift the list entry, the two row starts and f(v); per change the store
+    // of f(v) and the two predecessor-list starts; per push the list entry
+    st->model_bytes = st->relaxed_edges * (8 + vb) + st->lifts * (4 + 8 + vb) +
+                      st->changes * (vb + 8) + st->pushes * 4.0;
+    st->achieved_gbps = st->t_solve > 0 ? st->model_bytes / st->t_solve / 1e9 : 0;
+  }
+  if (status != EG_OK) return fail(status, "budget exhausted after %llu rounds", (unsigned long long)launched);
+  return EG_OK;
+}
+
+int eg_solve(eg_game* g, int64_t* credits, eg_stats* st) { return eg_solve_ex(g, nullptr, credits, st); }
+
+int eg_submit(eg_ctx* ctx, const eg_game_desc* desc, eg_ticket* out) {
+  if (!ctx || !desc || !out) return fail(EG_EINVAL, "null argument");
+  return eg::server_submit(ctx->server ? ctx->server : (ctx->server = eg::server_create(ctx->cfg, ctx->stream)),
+                           desc, out);
+}
+
+int eg_poll(eg_ctx* ctx, eg_ticket t, int64_t* credits, eg_stats* st) {
+  if (!ctx) return fail(EG_EINVAL, "null context");
+  if (!ctx->server) return fail(EG_ENOTFOUND, "unknown ticket %llu", (unsigned long long)t);
+  return eg::server_poll(ctx->server, t, credits, st);
+}
+
+int eg_cancel(eg_ctx* ctx, eg_ticket t) {
+  if (!ctx) return fail(EG_EINVAL, "null context");
+  if (!ctx->server) return fail(EG_ENOTFOUND, "unknown ticket %llu", (unsigned long long)t);
+  return eg::server_cancel(ctx->server, t);
+}
+
+}  // extern "C"

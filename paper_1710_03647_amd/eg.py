@@ -1,0 +1,273 @@
+"""Python binding of libeg (ctypes).  Argument marshalling only: every step of
+the solve runs in the library's HIP kernels.  Torch is used, when given, only
+for device buffers (``data_ptr``) and stream handles.
+
+Raises ``RuntimeError`` if ``libeg.so`` has not been built: there is no other
+implementation behind these calls.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libeg.so")
+HEADER = os.path.join(os.path.dirname(PKG), "include", "eg.h")
+
+EG_TOP = np.iinfo(np.int64).max
+EG_OK, EG_PENDING = 0, 1
+EG_EINVAL, EG_ENOMEM, EG_EDEVICE, EG_ETIMEDOUT, EG_EBUSY, EG_ENOTFOUND, EG_ECANCELED = -1, -2, -3, -4, -5, -6, -7
+EG_BOUND_NW, EG_BOUND_MG = 0, 1
+EG_MEM_HOST, EG_MEM_DEVICE = 0, 1
+ERROR_NAMES = {EG_EINVAL: "EG_EINVAL", EG_ENOMEM: "EG_ENOMEM", EG_EDEVICE: "EG_EDEVICE",
+               EG_ETIMEDOUT: "EG_ETIMEDOUT", EG_EBUSY: "EG_EBUSY", EG_ENOTFOUND: "EG_ENOTFOUND",
+               EG_ECANCELED: "EG_ECANCELED", EG_PENDING: "EG_PENDING"}
+
+EXPORTS = ["eg_ctx_create", "eg_ctx_destroy", "eg_check", "eg_create", "eg_destroy", "eg_solve",
+           "eg_solve_ex", "eg_set_measure", "eg_submit", "eg_poll", "eg_cancel", "eg_last_error"]
+
+
+class EgError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class eg_config(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int), ("hip_stream", ctypes.c_void_p),
+                ("hbm_budget_bytes", ctypes.c_uint64), ("max_slots", ctypes.c_int),
+                ("bound_mode", ctypes.c_int), ("max_rounds", ctypes.c_uint64),
+                ("time_budget_s", ctypes.c_double), ("max_pending", ctypes.c_int)]
+
+
+class eg_game_desc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int64), ("offsets", ctypes.c_void_p),
+                ("targets", ctypes.c_void_p), ("weights", ctypes.c_void_p),
+                ("owner_bits", ctypes.c_void_p), ("W", ctypes.c_int32), ("mem", ctypes.c_int)]
+
+
+class eg_stats(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_uint64), ("lifts", ctypes.c_uint64),
+                ("relaxed_edges", ctypes.c_uint64), ("pushes", ctypes.c_uint64),
+                ("changes", ctypes.c_uint64), ("t_upload", ctypes.c_double),
+                ("t_rcsr", ctypes.c_double), ("t_solve", ctypes.c_double), ("t_d2h", ctypes.c_double),
+                ("model_bytes", ctypes.c_double), ("achieved_gbps", ctypes.c_double)]
+
+    def to_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class eg_game_info(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int64), ("bound", ctypes.c_int64),
+                ("value_bits", ctypes.c_int), ("device_bytes", ctypes.c_uint64),
+                ("max_outdeg", ctypes.c_int32), ("max_indeg", ctypes.c_int32)]
+
+    def to_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class eg_solve_opts(ctypes.Structure):
+    _fields_ = [("max_rounds", ctypes.c_uint64), ("time_budget_s", ctypes.c_double),
+                ("resume", ctypes.c_int), ("driver", ctypes.c_int)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libeg (RuntimeError if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER
+        vp = ctypes.c_void_p
+        L.eg_ctx_create.argtypes = [P(eg_config), P(vp)]
+        L.eg_ctx_destroy.argtypes = [vp]
+        L.eg_check.argtypes = [P(eg_game_desc), ctypes.c_int, P(eg_game_info), ctypes.c_char_p, ctypes.c_size_t]
+        L.eg_create.argtypes = [vp, P(eg_game_desc), P(vp), P(eg_stats)]
+        L.eg_destroy.argtypes = [vp]
+        L.eg_solve.argtypes = [vp, vp, P(eg_stats)]
+        L.eg_solve_ex.argtypes = [vp, P(eg_solve_opts), vp, P(eg_stats)]
+        L.eg_set_measure.argtypes = [vp, vp]
+        L.eg_submit.argtypes = [vp, P(eg_game_desc), P(ctypes.c_uint64)]
+        L.eg_poll.argtypes = [vp, ctypes.c_uint64, vp, P(eg_stats)]
+        L.eg_cancel.argtypes = [vp, ctypes.c_uint64]
+        L.eg_last_error.argtypes = [vp]
+        L.eg_last_error.restype = ctypes.c_char_p
+        for name in EXPORTS[:-1]:
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _err(code: int, ctx=None) -> EgError:
+    msg = lib().eg_last_error(ctx)
+    return EgError(code, msg.decode() if msg else "")
+
+
+def _ptr(a) -> int:
+    if a is None:
+        return 0
+    if hasattr(a, "data_ptr"):
+        return int(a.data_ptr())
+    return int(a.ctypes.data)
+
+
+@dataclass
+class _HostGame:
+    """Host arrays of a game kept alive for the duration of a call."""
+    n: int
+    off: np.ndarray
+    tgt: np.ndarray
+    w: np.ndarray
+    bits: np.ndarray
+    W: int
+
+
+def _host_arrays(game) -> _HostGame:
+    off = np.ascontiguousarray(game.off, dtype=np.int64)
+    tgt = np.ascontiguousarray(game.tgt, dtype=np.int32)
+    w = np.ascontiguousarray(game.w, dtype=np.int32)
+    bits = np.ascontiguousarray(game.owner_bits(), dtype=np.uint8)
+    return _HostGame(int(game.n), off, tgt, w, bits, int(game.W))
+
+
+def make_desc(game=None, *, n=None, offsets=None, targets=None, weights=None, owner_bits=None, W=None,
+              device=False):
+    """Descriptor of a game.  Either a ``synth.Game`` (host arrays) or explicit
+    arrays (numpy for host, torch device tensors with ``device=True``).
+    Returns (desc, keepalive)."""
+    if game is not None:
+        h = _host_arrays(game)
+        d = eg_game_desc(h.n, int(h.off[-1]), _ptr(h.off), _ptr(h.tgt), _ptr(h.w), _ptr(h.bits), h.W,
+                         EG_MEM_HOST)
+        return d, h
+    m = int(targets.numel() if hasattr(targets, "numel") else len(targets))
+    d = eg_game_desc(int(n), m, _ptr(offsets), _ptr(targets), _ptr(weights), _ptr(owner_bits), int(W),
+                     EG_MEM_DEVICE if device else EG_MEM_HOST)
+    return d, (offsets, targets, weights, owner_bits)
+
+
+def check(game=None, bound_mode: int = EG_BOUND_NW, **arrays) -> dict:
+    """Host-only validation (eg_check).  Raises EgError(EG_EINVAL) on a bad game."""
+    desc, keep = make_desc(game, **arrays)
+    info = eg_game_info()
+    msg = ctypes.create_string_buffer(512)
+    rc = lib().eg_check(ctypes.byref(desc), bound_mode, ctypes.byref(info), msg, 512)
+    if rc != EG_OK:
+        raise EgError(rc, msg.value.decode())
+    return info.to_dict()
+
+
+class Context:
+    """An eg_ctx on one device.  ``stream`` may be a torch.cuda.Stream or a raw handle."""
+
+    def __init__(self, device: int = 0, stream=None, hbm_budget_bytes: int = 0, max_slots: int = 0,
+                 bound_mode: int = EG_BOUND_NW, max_rounds: int = 0, time_budget_s: float = 0.0,
+                 max_pending: int = 0):
+        handle = getattr(stream, "cuda_stream", stream) or 0
+        cfg = eg_config(device, handle, hbm_budget_bytes, max_slots, bound_mode, max_rounds, time_budget_s,
+                        max_pending)
+        p = ctypes.c_void_p()
+        rc = lib().eg_ctx_create(ctypes.byref(cfg), ctypes.byref(p))
+        if rc != EG_OK:
+            raise _err(rc)
+        self.handle = p
+        self.device = device
+
+    def close(self):
+        if self.handle:
+            lib().eg_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def create(self, game=None, **arrays) -> "Game":
+        desc, keep = make_desc(game, **arrays)
+        p = ctypes.c_void_p()
+        st = eg_stats()
+        rc = lib().eg_create(self.handle, ctypes.byref(desc), ctypes.byref(p), ctypes.byref(st))
+        if rc != EG_OK:
+            raise _err(rc, self.handle)
+        return Game(self, p, desc.n, st.to_dict())
+
+    # serving
+    def submit(self, game=None, **arrays) -> int:
+        desc, keep = make_desc(game, **arrays)
+        t = ctypes.c_uint64()
+        rc = lib().eg_submit(self.handle, ctypes.byref(desc), ctypes.byref(t))
+        if rc != EG_OK:
+            raise _err(rc, self.handle)
+        return int(t.value)
+
+    def poll(self, ticket: int, n: int):
+        """(status, credits or None, stats dict)."""
+        out = np.empty(n, dtype=np.int64)
+        st = eg_stats()
+        rc = lib().eg_poll(self.handle, ticket, _ptr(out), ctypes.byref(st))
+        if rc == EG_OK:
+            return rc, out, st.to_dict()
+        if rc == EG_PENDING:
+            return rc, None, None
+        raise _err(rc, self.handle)
+
+    def cancel(self, ticket: int) -> int:
+        return lib().eg_cancel(self.handle, ticket)
+
+
+class Game:
+    """A device-resident game (eg_game)."""
+
+    def __init__(self, ctx: Context, handle, n: int, create_stats: dict):
+        self.ctx = ctx
+        self.handle = handle
+        self.n = n
+        self.create_stats = create_stats
+
+    def solve(self, out=None, max_rounds: int = 0, time_budget_s: float = 0.0, resume: bool = False,
+              allow_timeout: bool = False):
+        """Solve to the least fixpoint.  Returns (credits int64[n], stats dict, status)."""
+        if out is None:
+            out = np.empty(self.n, dtype=np.int64)
+        st = eg_stats()
+        opts = eg_solve_opts(max_rounds, time_budget_s, 1 if resume else 0, 0)
+        rc = lib().eg_solve_ex(self.handle, ctypes.byref(opts), _ptr(out), ctypes.byref(st))
+        if rc != EG_OK and not (allow_timeout and rc == EG_ETIMEDOUT):
+            raise _err(rc, self.ctx.handle)
+        return out, st.to_dict(), rc
+
+    def set_measure(self, f: np.ndarray):
+        f = np.ascontiguousarray(f, dtype=np.int64)
+        rc = lib().eg_set_measure(self.handle, _ptr(f))
+        if rc != EG_OK:
+            raise _err(rc, self.ctx.handle)
+
+    def destroy(self):
+        if self.handle:
+            lib().eg_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.destroy()
+
+
+def solve(game, device: int = 0, **kw):
+    """One-shot helper: create a context and a game, solve, clean up."""
+    with Context(device) as ctx:
+        g = ctx.create(game)
+        try:
+            return g.solve(**kw)
+        finally:
+            g.destroy()

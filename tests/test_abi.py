@@ -1,0 +1,129 @@
+"""The C-ABI library loads, exports every declared entry point, and validates
+games on the host without a device (no GPU needed)."""
+import ctypes
+import re
+
+import numpy as np
+import pytest
+
+from paper_1710_03647_amd import eg, synth
+
+
+@pytest.fixture(scope="module")
+def L():
+    return eg.lib()
+
+
+def declared_functions():
+    text = open(eg.HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(eg_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_exports_every_declared_symbol(L):
+    names = declared_functions()
+    assert len(names) >= 12
+    for name in names:
+        assert hasattr(L, name), name
+    assert sorted(eg.EXPORTS) == names
+
+
+def _desc(n, off, tgt, w, bits, W):
+    keep = [np.ascontiguousarray(off, np.int64), np.ascontiguousarray(tgt, np.int32),
+            np.ascontiguousarray(w, np.int32), np.ascontiguousarray(bits, np.uint8)]
+    d = eg.eg_game_desc(n, int(keep[0][-1]) if len(keep[0]) else 0, keep[0].ctypes.data,
+                        keep[1].ctypes.data, keep[2].ctypes.data, keep[3].ctypes.data, W, eg.EG_MEM_HOST)
+    return d, keep
+
+
+def _check(L, d, bound_mode=0):
+    info = eg.eg_game_info()
+    msg = ctypes.create_string_buffer(256)
+    rc = L.eg_check(ctypes.byref(d), bound_mode, ctypes.byref(info), msg, 256)
+    return rc, msg.value.decode(), info
+
+
+def test_valid_game_info(L):
+    g = synth.gen_plain()
+    info = eg.check(g)
+    assert info["n"] == 1000 and info["m"] == 4000 and info["bound"] == 9990
+    assert info["value_bits"] == 32 and info["max_outdeg"] == 4
+    assert info["max_indeg"] == np.bincount(g.tgt, minlength=g.n).max()
+
+
+def test_bound_modes(L, oracle_mod):
+    g = synth.gen_uniform(500, 3, 50, 3)
+    assert eg.check(g)["bound"] == oracle_mod.bound_of(g, 0) == 499 * 50
+    assert eg.check(g, bound_mode=eg.EG_BOUND_MG)["bound"] == oracle_mod.bound_of(g, 1)
+
+
+def test_value_width_choice():
+    # B + 2W + 1 < 2^31 gives 32-bit storage; the R-MAT bound needs 64 bits
+    assert eg.check(synth.gen_uniform(1 << 12, 4, 1000, 1))["value_bits"] == 32
+    g = synth.gen_uniform(300000, 1, 10000, 1)  # B = 2_999_990_000 > 2^31
+    assert eg.check(g)["value_bits"] == 64
+
+
+@pytest.mark.parametrize("case", ["n0", "off0", "offn", "decreasing", "target_hi", "target_neg",
+                                  "not_total", "W_small", "W_negative", "m_huge", "null", "bound_mode"])
+def test_invalid_games_rejected(L, case):
+    n = 4
+    off = np.array([0, 1, 2, 3, 4])
+    tgt = np.array([1, 2, 3, 0])
+    w = np.array([-2, 1, 0, 3])
+    bits = np.array([0b0101], np.uint8)
+    W = 2
+    mode = 0
+    if case == "n0":
+        n = 0
+    elif case == "off0":
+        off = np.array([1, 1, 2, 3, 4])
+    elif case == "offn":
+        off = np.array([0, 1, 2, 3, 3])
+    elif case == "decreasing":
+        off = np.array([0, 2, 1, 3, 4])
+    elif case == "target_hi":
+        tgt = np.array([1, 2, 4, 0])
+    elif case == "target_neg":
+        tgt = np.array([1, -1, 3, 0])
+    elif case == "not_total":
+        off = np.array([0, 1, 1, 3, 4])
+    elif case == "W_small":
+        W = 1
+    elif case == "W_negative":
+        W = -1
+    elif case == "bound_mode":
+        mode = 7
+    d, keep = _desc(n, off, tgt, w, bits, W)
+    if case == "m_huge":
+        d.m = 1 << 31
+    if case == "null":
+        d.targets = None
+    rc, msg, _ = _check(L, d, mode)
+    assert rc == eg.EG_EINVAL, (case, rc, msg)
+    assert msg
+    assert L.eg_last_error(None).decode() == msg
+
+
+def test_duplicates_and_self_loops_allowed(L):
+    g = synth.make_game(2, [(0, 0, -1), (0, 0, -1), (0, 1, 3), (1, 1, 0)], [0, 1], W=1)
+    info = eg.check(g)
+    assert info["m"] == 4
+
+
+def test_device_pointers_rejected_by_check(L):
+    d, keep = _desc(1, [0, 1], [0], [0], [0], 0)
+    d.mem = eg.EG_MEM_DEVICE
+    rc, msg, _ = _check(L, d)
+    assert rc == eg.EG_EINVAL
+
+
+def test_no_device_fails_loudly():
+    """Without a usable GPU the context cannot be created: an error, never a
+    silent fallback."""
+    import torch
+
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(eg.EgError) as ei:
+        eg.Context(0)
+    assert ei.value.code == eg.EG_EDEVICE
