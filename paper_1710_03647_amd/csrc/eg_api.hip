@@ -48,7 +48,8 @@ void set_error(const char* msg) { t_err = msg; }
 const char* get_error() { return t_err.c_str(); }
 
 // Host-side validation of a game (host pointers).  Fills info; 0 or EG_EINVAL.
-int check_host(const eg_game_desc* d, int bound_mode, eg_game_info* info, std::string* why) {
+int check_host(const eg_game_desc* d, int bound_mode, eg_game_info* info, std::string* why,
+               int64_t* clamp_out) {
   auto bad = [&](const char* fmt, auto... a) {
     char buf[256];
     snprintf(buf, sizeof buf, fmt, a...);
@@ -68,7 +69,7 @@ int check_host(const eg_game_desc* d, int bound_mode, eg_game_info* info, std::s
   if (off[n] != d->m) return bad("offsets[n] = %lld, must equal m = %lld", (long long)off[n], (long long)d->m);
   int32_t max_out = 0;
   int64_t mg = 0;
-  int32_t most_negative = 0;
+  int32_t most_negative = 0, most_positive = 0;
   for (int32_t v = 0; v < n; v++) {
     const int64_t a = off[v], b = off[v + 1];
     if (b < a) return bad("offsets decrease at vertex %d", v);
@@ -80,6 +81,7 @@ int check_host(const eg_game_desc* d, int bound_mode, eg_game_info* info, std::s
       if (t < 0 || t >= n) return bad("edge %lld of vertex %d targets %d, outside [0, %d)", (long long)e, v, t, n);
       const int32_t w = d->weights[e];
       if (w < 0 && -(int64_t)w > worst) worst = (int32_t)std::min<int64_t>(-(int64_t)w, INT32_MAX);
+      if (w > most_positive) most_positive = w;
     }
     mg += worst;
     most_negative = std::max(most_negative, worst);
@@ -87,9 +89,14 @@ int check_host(const eg_game_desc* d, int bound_mode, eg_game_info* info, std::s
   if ((int64_t)d->W < most_negative)
     return bad("W = %d is below the largest negative weight magnitude %d", d->W, most_negative);
   const int64_t bound = bound_mode == EG_BOUND_MG ? mg : (int64_t)(n - 1) * (int64_t)d->W;
-  // TOP is encoded as B + W + 1 and a term reaches at most B + 2W + 1
-  const __int128 hi = (__int128)bound + 2 * (__int128)d->W + 1;
-  if (hi > (__int128)INT64_MAX) return bad("bound %lld + 2W + 1 overflows int64", (long long)bound);
+  // On the device positive weights are clamped to P = min(max w, B + 1), which
+  // leaves every finite term max(0, f(u) - w) with f(u) <= B unchanged, and TOP
+  // is encoded as B + P + 1 so that TOP - w > B for every stored w.  The largest
+  // intermediate value is then TOP + W.
+  const int64_t clamp = std::min<int64_t>(most_positive, bound + 1);
+  const __int128 hi = (__int128)bound + clamp + 1 + (__int128)d->W;
+  if (hi > (__int128)INT64_MAX) return bad("bound %lld too large for int64 arithmetic", (long long)bound);
+  if (clamp_out) *clamp_out = clamp;
   std::vector<int32_t> indeg(n, 0);
   int32_t max_in = 0;
   for (int64_t e = 0; e < d->m; e++) max_in = std::max(max_in, ++indeg[d->targets[e]]);
@@ -148,7 +155,7 @@ int eg_check(const eg_game_desc* desc, int bound_mode, eg_game_info* info, char*
     if (msg && msg_len) snprintf(msg, msg_len, "%s", why.c_str());
     return fail(EG_EINVAL, "%s", why.c_str());
   }
-  int rc = eg::check_host(desc, bound_mode, info, &why);
+  int rc = eg::check_host(desc, bound_mode, info, &why, nullptr);
   if (msg && msg_len) snprintf(msg, msg_len, "%s", why.c_str());
   if (rc != EG_OK) return fail(rc, "%s", why.c_str());
   return EG_OK;
@@ -239,7 +246,9 @@ int eg_create(eg_ctx* ctx, const eg_game_desc* desc, eg_game** out, eg_stats* st
   }
   eg_game_info info{};
   std::string why;
-  if (eg::check_host(&hd, ctx->cfg.bound_mode, &info, &why) != EG_OK) return fail(EG_EINVAL, "%s", why.c_str());
+  int64_t clamp = 0;
+  if (eg::check_host(&hd, ctx->cfg.bound_mode, &info, &why, &clamp) != EG_OK)
+    return fail(EG_EINVAL, "%s", why.c_str());
 
   eg_game* g = new eg_game();
   g->ctx = ctx;
@@ -280,7 +289,7 @@ int eg_create(eg_ctx* ctx, const eg_game_desc* desc, eg_game** out, eg_stats* st
   dg.ctrl = (uint32_t*)(base + offs[9]);
   dg.stats = (unsigned long long*)(base + offs[10]);
   dg.bound = g->bound;
-  dg.top = g->bound + g->W + 1;
+  dg.top = g->bound + clamp + 1;
 
   auto cleanup_fail = [&](int code, const char* what, hipError_t err) {
     game_free(g);
@@ -322,8 +331,8 @@ int eg_create(eg_ctx* ctx, const eg_game_desc* desc, eg_game** out, eg_stats* st
       if (mm && (r = hipMemcpyAsync((void*)d_w, desc->weights, 4 * mm, hipMemcpyHostToDevice, s))) return r;
       if ((r = hipMemcpyAsync((void*)d_own, desc->owner_bits, (nn + 7) / 8, hipMemcpyHostToDevice, s))) return r;
     }
-    if ((r = eg::launch_layout(d_off, d_own, d_tgt, d_w, g->n, (uint32_t)mm, (uint32_t*)dg.rs,
-                               (int2*)dg.edges, s)) != hipSuccess) return r;
+    if ((r = eg::launch_layout(d_off, d_own, d_tgt, d_w, g->n, (uint32_t)mm, (int32_t)clamp,
+                               (uint32_t*)dg.rs, (int2*)dg.edges, s)) != hipSuccess) return r;
     if ((r = hipEventRecord(g->ev[1], s)) != hipSuccess) return r;
     if ((r = eg::launch_reverse_csr(dg.rs, dg.edges, g->n, (uint32_t)mm, (uint32_t*)dg.rev_off,
                                     (int32_t*)dg.rev_src, cursor, scan_tmp, scan_words, s)) != hipSuccess)

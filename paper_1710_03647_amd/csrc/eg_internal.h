@@ -36,13 +36,13 @@ struct DevGame {
   uint32_t* ctrl;           // C_WORDS
   unsigned long long* stats;  // S_WORDS
   int64_t bound;            // B
-  int64_t top;              // device encoding of TOP: B + W + 1
+  int64_t top;              // device encoding of TOP: B + P + 1, P = largest stored weight
 };
 
 // Layout and predecessor lists (eg_kernels.hip)
 hipError_t launch_layout(const int64_t* off, const uint8_t* owner_bits, const int32_t* tgt,
-                         const int32_t* w, int32_t n, uint32_t m, uint32_t* rs, int2* edges,
-                         hipStream_t s);
+                         const int32_t* w, int32_t n, uint32_t m, int32_t wclamp, uint32_t* rs,
+                         int2* edges, hipStream_t s);
 hipError_t launch_reverse_csr(const uint32_t* rs, const int2* edges, int32_t n, uint32_t m,
                               uint32_t* rev_off, int32_t* rev_src, uint32_t* cursor,
                               uint32_t* scan_tmp, size_t scan_tmp_words, hipStream_t s);

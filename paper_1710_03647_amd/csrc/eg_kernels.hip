@@ -3,9 +3,10 @@
 // Layout:   rs[v] = row start of v | owner bit,  edges[e] = {target, weight}
 // Reverse:  rev_off / rev_src = predecessor lists, one entry per edge (the
 //           paper's redundant CSC of Sec. 5), built by histogram + scan + scatter.
-// Solve:    f values of width V (int32 when B + 2W + 1 < 2^31, else int64);
-//           TOP is encoded as B + W + 1, so for any edge f(u) - w(v,u) > B
-//           exactly when f(u) is TOP or the finite term leaves C_G.
+// Solve:    f values of width V (int32 when TOP + W < 2^31, else int64);
+//           stored weights are at most P = min(max weight, B + 1) and TOP is
+//           encoded as B + P + 1, so for any edge f(u) - w(v,u) > B exactly
+//           when f(u) is TOP or the finite term leaves C_G.
 #include <limits>
 
 #include "eg_internal.h"
@@ -48,19 +49,22 @@ __global__ void k_layout_rows(const int64_t* off, const uint8_t* owner_bits, int
   }
 }
 
-__global__ void k_layout_edges(const int32_t* tgt, const int32_t* w, uint32_t m, int2* edges) {
+// Weights above `wclamp` (>= the bound + 1 or the largest weight) are stored as
+// wclamp: for a finite f(u) <= B both give the term 0.
+__global__ void k_layout_edges(const int32_t* tgt, const int32_t* w, uint32_t m, int32_t wclamp,
+                               int2* edges) {
   for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < m; e += gridDim.x * blockDim.x)
-    edges[e] = make_int2(tgt[e], w[e]);
+    edges[e] = make_int2(tgt[e], min(w[e], wclamp));
 }
 
 hipError_t launch_layout(const int64_t* off, const uint8_t* owner_bits, const int32_t* tgt,
-                         const int32_t* w, int32_t n, uint32_t m, uint32_t* rs, int2* edges,
-                         hipStream_t s) {
+                         const int32_t* w, int32_t n, uint32_t m, int32_t wclamp, uint32_t* rs,
+                         int2* edges, hipStream_t s) {
   const int grid_v = (int)std::min<int64_t>(((int64_t)n + BLOCK) / BLOCK, 8192);
   hipLaunchKernelGGL(k_layout_rows, dim3(grid_v), dim3(BLOCK), 0, s, off, owner_bits, n, m, rs);
   if (m > 0) {
     const int grid_e = (int)std::min<int64_t>(((int64_t)m + BLOCK - 1) / BLOCK, 16384);
-    hipLaunchKernelGGL(k_layout_edges, dim3(grid_e), dim3(BLOCK), 0, s, tgt, w, m, edges);
+    hipLaunchKernelGGL(k_layout_edges, dim3(grid_e), dim3(BLOCK), 0, s, tgt, w, m, wclamp, edges);
   }
   return hipGetLastError();
 }

@@ -81,6 +81,13 @@ def lib():
     """The loaded libeg (RuntimeError if it was not built)."""
     global _lib
     if _lib is None:
+        try:
+            # One HIP runtime per process: when torch is installed its runtime is
+            # loaded first and libeg binds to it, so torch streams and device
+            # pointers can be handed to libeg.
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
         L = ctypes.CDLL(LIB_PATH)

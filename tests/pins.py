@@ -146,6 +146,17 @@ def pin_cf6_top_propagation(solve):
     expect_equal(solve(g), [TOP, TOP, TOP], "CF6 p0 all top")
 
 
+def pin_cf6b_positive_weight_into_top(solve):
+    """Positive weights above W (W only bounds the negative ones) into a TOP
+    successor still give TOP: TOP (-) b = TOP for every b."""
+    for big in (2, 7, 1000, 2 ** 31 - 1):
+        # 1 is a -1 self-loop trap; 0 can only move to 1, with weight +big
+        g = synth.make_game(3, [(0, 1, big), (1, 1, -1), (2, 0, big), (2, 2, -1)], [0, 1, 1], W=1)
+        expect_equal(solve(g), [TOP, TOP, TOP], f"CF6b big={big}")
+        g = synth.make_game(3, [(0, 1, big), (0, 2, big), (1, 1, -1), (2, 2, 0)], [0, 0, 0], W=1)
+        expect_equal(solve(g), [0, TOP, 0], f"CF6b choice big={big}")
+
+
 def pin_cf7_sign(solve):
     """All weights >= 0: every credit 0.  All weights < 0: every vertex TOP."""
     for seed in (1, 2, 3):
@@ -179,7 +190,7 @@ def pin_cf9_one_player(solve, trials=60, seed=9):
 
 
 CLOSED_FORMS = [pin_cf1_self_loop, pin_cf2_chain, pin_cf3_tight_chain, pin_cf4_cycle, pin_cf5_choice,
-                pin_cf6_top_propagation, pin_cf7_sign, pin_cf8_climb, pin_cf9_one_player]
+                pin_cf6_top_propagation, pin_cf6b_positive_weight_into_top, pin_cf7_sign, pin_cf8_climb, pin_cf9_one_player]
 
 
 # --------------------------------------------------------------------------- fixpoint (numpy)
