@@ -1,0 +1,205 @@
+#!/usr/bin/env python3
+"""Benchmark: GTEPS to the least fixpoint of one energy game on one MI355X.
+
+A step is one eg_solve of the whole game (init, every round to the fixpoint,
+result conversion and copy to the host) on a game already resident in device
+memory.  value = relaxed edges over the K timed steps / their wall time / 1e9.
+
+The default workload is the uniform random game (n = 2^20, out-degree 16,
+weights uniform in [-1000, 1000], owners Bernoulli(0.5), seed 2).  Synthetic,
+seeded input: the paper's instances are not available.
+
+Also reported:
+  roofline      the round kernels' algorithmic bytes over their device time,
+                against the 8 TB/s HBM peak; `traffic` from committed rocprofv3
+                counter summaries when they match the current kernel source;
+  cpu_baseline  the CPU oracle (sequential FIFO worklist, one core) on a
+                bounded sample of the same game: its first lifts, ~15 s of work.
+
+Flags: --gpus N (only 1 is supported: the solver runs on one GPU),
+--steps K, --warmup W, --config {uniform,plain,rmat,torus}, --no-cpu-baseline,
+--sweep R (instead of solves: R full-frontier lift rounds, every vertex active),
+--max-rounds M (profiling only: stops each solve after M rounds; the line is
+then marked partial).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+METRIC = "GTEPS to fixpoint (1 game); batched games/sec with p50/p99 latency"
+KERNEL_SRC = os.path.join(ROOT, "paper_1710_03647_amd", "csrc", "eg_kernels.hip")
+TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_game(name):
+    from paper_1710_03647_amd import synth
+
+    if name == "uniform":
+        g = synth.gen_uniform_full()
+        desc = "uniform random game: n=1048576, out-degree 16, weights uniform in [-1000,1000], owners Bernoulli(0.5), seed 2"
+    elif name == "plain":
+        g = synth.gen_plain()
+        desc = "plain game: n=1000, out-degree 4, weights uniform in [-10,10], owners Bernoulli(0.5), seed 1"
+    elif name == "rmat":
+        g = synth.gen_rmat_full()
+        desc = "R-MAT scale 22, edge factor 16, (.57,.19,.19,.05), sink self-loops, weights in [-10000,10000], seed 3"
+    elif name == "torus":
+        g = synth.gen_torus_full()
+        desc = "2048x2048 directed torus, weights uniform in [-100,100]+2, owners Bernoulli(0.5), seed 4"
+    else:
+        raise SystemExit(f"unknown config {name}")
+    return g, desc
+
+
+def kernel_hash():
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def traffic_for(config):
+    """HBM bytes per round launch from the committed counter summary, if it was
+    taken on the current kernel source."""
+    if not os.path.exists(TRAFFIC):
+        return None
+    try:
+        t = json.load(open(TRAFFIC))
+    except ValueError:
+        return None
+    e = t.get(config)
+    if not e or e.get("kernel_sha") != kernel_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def cpu_baseline(game, seconds):
+    from oracle import oracle
+
+    oracle.build()
+    probe = oracle.solve(game, max_lifts=200_000)
+    t0 = time.perf_counter()
+    probe = oracle.solve(game, max_lifts=200_000)
+    dt = time.perf_counter() - t0
+    lifts = max(200_000, int(200_000 * seconds / max(dt, 1e-6)))
+    t0 = time.perf_counter()
+    r = oracle.solve(game, max_lifts=lifts)
+    dt = time.perf_counter() - t0
+    done = "to the fixpoint" if r.status == 0 else f"its first {r.lifts} lifts"
+    return {"value": r.relaxed_edges / dt / 1e9, "unit": "GTEPS", "cores": 1, "kind": "oracle",
+            "sample": f"sequential FIFO worklist on the same game, {done} ({r.relaxed_edges} relaxed edges, "
+                      f"{dt:.1f} s, one thread)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--config", default="uniform")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--sweep", type=int, default=0)
+    ap.add_argument("--max-rounds", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: --gpus {args.gpus} is not supported; the solver runs on one GPU "
+              f"(games are independent: several GPUs would serve separate games)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1710_03647_amd import eg
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+    game, desc = make_game(args.config)
+    info = eg.check(game)
+    log(f"[bench] {desc}: n={game.n} m={game.m} bound={info['bound']} value_bits={info['value_bits']}")
+
+    ctx = eg.Context(0, stream=stream)
+    # kernels loaded once, untimed (a small game)
+    from paper_1710_03647_amd import synth
+
+    with ctx.create(synth.gen_plain()) as g0:
+        g0.solve()
+    t0 = time.perf_counter()
+    g = ctx.create(game)
+    log(f"[bench] create: {time.perf_counter() - t0:.2f} s (upload {g.create_stats['t_upload'] * 1e3:.1f} ms, "
+        f"reverse CSR {g.create_stats['t_rcsr'] * 1e3:.1f} ms)")
+    out = np.empty(game.n, dtype=np.int64)
+    partial = bool(args.max_rounds)
+
+    def step():
+        if args.sweep:
+            f, st, rc = g.solve(out=out, max_rounds=1, resume=True, allow_timeout=True)
+        else:
+            f, st, rc = g.solve(out=out, max_rounds=args.max_rounds, allow_timeout=partial)
+        return st
+
+    for i in range(args.warmup):
+        st = step()
+        log(f"[bench] warmup {i}: {st['t_solve']:.3f} s, rounds {st['rounds']}")
+    steps = args.sweep or args.steps
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    agg = dict(relaxed_edges=0, rounds=0, t_round_kernels=0.0, launched_rounds=0, model_bytes=0.0, lifts=0)
+    for i in range(steps):
+        st = step()
+        for k in agg:
+            agg[k] += st[k]
+        if not args.sweep:
+            log(f"[bench] step {i}: t_solve {st['t_solve']:.3f} s, rounds {st['rounds']} "
+                f"(dense {st['dense_rounds']}), relaxed edges {st['relaxed_edges']}, "
+                f"kernel time {st['t_round_kernels']:.3f} s")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    value = agg["relaxed_edges"] / wall / 1e9
+    achieved = agg["model_bytes"] / agg["t_round_kernels"] / 1e9 if agg["t_round_kernels"] else 0.0
+    traffic = traffic_for(args.config)
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "GTEPS",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32" if info["value_bits"] == 32 else "int64",
+        "data": "synthetic",
+        "config": {"workload": desc, "n": game.n, "m": game.m, "W": game.W, "bound": info["bound"],
+                   "mode": "full-frontier lift rounds" if args.sweep else "solve to fixpoint",
+                   "rounds_per_step": agg["rounds"] / steps},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
+                     "kernel": "k_round (lift + predecessor activation, one launch per round)",
+                     "bytes_per_launch": agg["model_bytes"] / max(1, agg["launched_rounds"]),
+                     "us_per_launch": agg["t_round_kernels"] / max(1, agg["launched_rounds"]) * 1e6},
+    }
+    if partial:
+        line["partial"] = f"solves stopped after {args.max_rounds} rounds (profiling run)"
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(game, args.cpu_seconds)
+    g.destroy()
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

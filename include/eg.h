@@ -94,12 +94,16 @@ typedef struct {
   uint64_t relaxed_edges; /* out-edges read by those lifts (GTEPS = relaxed_edges / t_solve) */
   uint64_t pushes;        /* insertions into the next active set */
   uint64_t changes;       /* lifts that raised a value */
+  uint64_t scanned_preds; /* predecessor-list entries read after those changes */
   double t_upload;        /* eg_create: host-to-device copy and layout, seconds */
   double t_rcsr;          /* eg_create: reverse CSR (predecessor lists) build, seconds */
   double t_solve;         /* eg_solve: from the init launch to the fixpoint, seconds */
   double t_d2h;           /* eg_solve: result conversion and device-to-host copy, seconds */
-  double model_bytes;     /* algorithmic bytes moved by the solve (see DESIGN) */
+  double model_bytes;     /* algorithmic bytes moved by the solve (see eg_solve_ex) */
   double achieved_gbps;   /* model_bytes / t_solve / 1e9 */
+  double t_round_kernels; /* device time of the round kernels alone, seconds */
+  uint64_t launched_rounds; /* round kernels launched (empty ones after the fixpoint included) */
+  uint64_t dense_rounds;  /* of which in the dense representation */
 } eg_stats;
 
 /* What eg_check derives from a valid game. */

@@ -49,7 +49,7 @@ const char* get_error() { return t_err.c_str(); }
 
 // Host-side validation of a game (host pointers).  Fills info; 0 or EG_EINVAL.
 int check_host(const eg_game_desc* d, int bound_mode, eg_game_info* info, std::string* why,
-               int64_t* clamp_out) {
+               int64_t* clamp_out, std::vector<uint32_t>* act_bits) {
   auto bad = [&](const char* fmt, auto... a) {
     char buf[256];
     snprintf(buf, sizeof buf, fmt, a...);
@@ -70,19 +70,26 @@ int check_host(const eg_game_desc* d, int bound_mode, eg_game_info* info, std::s
   int32_t max_out = 0;
   int64_t mg = 0;
   int32_t most_negative = 0, most_positive = 0;
+  if (act_bits) act_bits->assign(((size_t)n + 31) / 32, 0u);
   for (int32_t v = 0; v < n; v++) {
     const int64_t a = off[v], b = off[v + 1];
     if (b < a) return bad("offsets decrease at vertex %d", v);
     if (b == a) return bad("vertex %d has no out-edge: the arena is not total", v);
     max_out = std::max<int32_t>(max_out, (int32_t)std::min<int64_t>(b - a, INT32_MAX));
     int32_t worst = 0;
+    int64_t negatives = 0;
     for (int64_t e = a; e < b; e++) {
       const int32_t t = d->targets[e];
       if (t < 0 || t >= n) return bad("edge %lld of vertex %d targets %d, outside [0, %d)", (long long)e, v, t, n);
       const int32_t w = d->weights[e];
       if (w < 0 && -(int64_t)w > worst) worst = (int32_t)std::min<int64_t>(-(int64_t)w, INT32_MAX);
       if (w > most_positive) most_positive = w;
+      negatives += w < 0;
     }
+    // initial active set of Alg. 3 (line 3) and Alg. 1 (lines 1-2): player 0 with
+    // every out-edge negative, player 1 with some negative out-edge
+    const bool p1 = (d->owner_bits[v >> 3] >> (v & 7)) & 1;
+    if (act_bits && (p1 ? negatives > 0 : negatives == b - a)) (*act_bits)[v >> 5] |= 1u << (v & 31);
     mg += worst;
     most_negative = std::max(most_negative, worst);
   }
@@ -139,9 +146,13 @@ struct eg_game {
   void* arena = nullptr;
   eg::DevGame dg{};
   int64_t* out64 = nullptr;
+  size_t arena_bytes = 0;
+  int grid = 1;
+  double avg_indeg = 1;
+  uint32_t* h_blk = nullptr;
   uint32_t* h_ctrl = nullptr;
   unsigned long long* h_stats = nullptr;
-  hipEvent_t ev[4] = {};
+  hipEvent_t ev[6] = {};
 };
 
 extern "C" {
@@ -155,7 +166,7 @@ int eg_check(const eg_game_desc* desc, int bound_mode, eg_game_info* info, char*
     if (msg && msg_len) snprintf(msg, msg_len, "%s", why.c_str());
     return fail(EG_EINVAL, "%s", why.c_str());
   }
-  int rc = eg::check_host(desc, bound_mode, info, &why, nullptr);
+  int rc = eg::check_host(desc, bound_mode, info, &why, nullptr, nullptr);
   if (msg && msg_len) snprintf(msg, msg_len, "%s", why.c_str());
   if (rc != EG_OK) return fail(rc, "%s", why.c_str());
   return EG_OK;
@@ -205,6 +216,7 @@ static void game_free(eg_game* g) {
   if (!g) return;
   if (g->arena) hipFree(g->arena);
   if (g->h_ctrl) hipHostFree(g->h_ctrl);
+  if (g->h_blk) hipHostFree(g->h_blk);
   if (g->h_stats) hipHostFree(g->h_stats);
   for (auto& e : g->ev)
     if (e) hipEventDestroy(e);
@@ -247,7 +259,8 @@ int eg_create(eg_ctx* ctx, const eg_game_desc* desc, eg_game** out, eg_stats* st
   eg_game_info info{};
   std::string why;
   int64_t clamp = 0;
-  if (eg::check_host(&hd, ctx->cfg.bound_mode, &info, &why, &clamp) != EG_OK)
+  std::vector<uint32_t> act_bits;
+  if (eg::check_host(&hd, ctx->cfg.bound_mode, &info, &why, &clamp, &act_bits) != EG_OK)
     return fail(EG_EINVAL, "%s", why.c_str());
 
   eg_game* g = new eg_game();
@@ -261,10 +274,15 @@ int eg_create(eg_ctx* ctx, const eg_game_desc* desc, eg_game** out, eg_stats* st
   g->h = eg::pick_h((double)desc->m / desc->n);
   const size_t nn = (size_t)g->n, mm = (size_t)g->m, vb = g->vbits / 8;
   // one device allocation holds everything the game keeps
-  size_t offs[11], total = 0;
-  const size_t sizes[11] = {4 * (nn + 1), 8 * mm, 4 * (nn + 1), 4 * mm, vb * nn, 4 * nn, 4 * nn, 4 * nn,
-                            8 * nn, 4 * eg::C_WORDS, 8 * eg::S_WORDS};
-  for (int i = 0; i < 11; i++) {
+  const size_t nblk = (size_t)std::max(1, std::min<int>(ctx->grid, (int)((nn + eg::TILE_VERTICES - 1) / eg::TILE_VERTICES)));
+  g->grid = (int)nblk;
+  // one device allocation holds everything the game keeps
+  enum { A_RS, A_EDGES, A_ROFF, A_RSRC, A_F, A_STAMP, A_WL0, A_WL1, A_OUT, A_CTRL, A_STATS, A_ACT, A_BLK, A_SLOTS, A_N };
+  size_t offs[A_N], total = 0;
+  const size_t sizes[A_N] = {4 * (nn + 1), 8 * mm, 4 * (nn + 1), 4 * mm, vb * nn, 2 * align_up(nn + 4), 4 * nn, 4 * nn,
+                             8 * nn, 4 * eg::C_WORDS, 8 * eg::S_WORDS, 4 * act_bits.size(), 4 * nblk,
+                             8 * eg::S_WORDS * nblk};
+  for (int i = 0; i < A_N; i++) {
     offs[i] = total;
     total += align_up(std::max<size_t>(sizes[i], 4));
   }
@@ -273,23 +291,29 @@ int eg_create(eg_ctx* ctx, const eg_game_desc* desc, eg_game** out, eg_stats* st
     game_free(g);
     return fail(EG_ENOMEM, "device allocation of %zu bytes failed: %s", total, hipGetErrorString(e));
   }
+  g->arena_bytes = total;
   char* base = (char*)g->arena;
   eg::DevGame& dg = g->dg;
   dg.n = g->n;
   dg.m = (uint32_t)g->m;
-  dg.rs = (uint32_t*)(base + offs[0]);
-  dg.edges = (int2*)(base + offs[1]);
-  dg.rev_off = (uint32_t*)(base + offs[2]);
-  dg.rev_src = (int32_t*)(base + offs[3]);
-  dg.f = base + offs[4];
-  dg.stamp = (uint32_t*)(base + offs[5]);
-  dg.wl0 = (int32_t*)(base + offs[6]);
-  dg.wl1 = (int32_t*)(base + offs[7]);
-  g->out64 = (int64_t*)(base + offs[8]);
-  dg.ctrl = (uint32_t*)(base + offs[9]);
-  dg.stats = (unsigned long long*)(base + offs[10]);
+  dg.rs = (uint32_t*)(base + offs[A_RS]);
+  dg.edges = (int2*)(base + offs[A_EDGES]);
+  dg.rev_off = (uint32_t*)(base + offs[A_ROFF]);
+  dg.rev_src = (int32_t*)(base + offs[A_RSRC]);
+  dg.f = base + offs[A_F];
+  dg.act0 = (uint8_t*)(base + offs[A_STAMP]);
+  dg.act1 = dg.act0 + align_up(nn + 4);
+  dg.wl0 = (int32_t*)(base + offs[A_WL0]);
+  dg.wl1 = (int32_t*)(base + offs[A_WL1]);
+  g->out64 = (int64_t*)(base + offs[A_OUT]);
+  dg.ctrl = (uint32_t*)(base + offs[A_CTRL]);
+  dg.stats = (unsigned long long*)(base + offs[A_STATS]);
+  dg.act_bits = (const uint32_t*)(base + offs[A_ACT]);
+  dg.blk_chg = (uint32_t*)(base + offs[A_BLK]);
+  dg.slots = (unsigned long long*)(base + offs[A_SLOTS]);
   dg.bound = g->bound;
   dg.top = g->bound + clamp + 1;
+  g->avg_indeg = (double)mm / (double)nn;
 
   auto cleanup_fail = [&](int code, const char* what, hipError_t err) {
     game_free(g);
@@ -301,6 +325,11 @@ int eg_create(eg_ctx* ctx, const eg_game_desc* desc, eg_game** out, eg_stats* st
     return cleanup_fail(EG_EDEVICE, "hipHostMalloc", e);
   for (auto& ev : g->ev)
     if ((e = hipEventCreate(&ev)) != hipSuccess) return cleanup_fail(EG_EDEVICE, "hipEventCreate", e);
+  if ((e = hipHostMalloc((void**)&g->h_blk, 4 * nblk, hipHostMallocDefault)) != hipSuccess)
+    return cleanup_fail(EG_EDEVICE, "hipHostMalloc", e);
+  if ((e = hipMemcpyAsync((void*)dg.act_bits, act_bits.data(), 4 * act_bits.size(), hipMemcpyHostToDevice, s)) !=
+      hipSuccess)
+    return cleanup_fail(EG_EDEVICE, "upload of the initial active set", e);
 
   // staging for the raw inputs (host path) plus reverse-CSR scratch
   const size_t scan_words = eg::scan_tmp_words(nn + 1);
@@ -376,6 +405,11 @@ int eg_set_measure(eg_game* g, const int64_t* f) {
   return EG_OK;
 }
 
+// Rounds run in batches enqueued without waiting; after each batch the host
+// reads the control words and the per-block change counts to detect the
+// fixpoint (an empty active set) and to choose the representation of the next
+// batch: dense while the active set is a large fraction of V, sparse (a list)
+// otherwise.  Extra rounds enqueued after the fixpoint find no work and return.
 int eg_solve_ex(eg_game* g, const eg_solve_opts* opts, int64_t* credits, eg_stats* st) {
   if (!g) return fail(EG_EINVAL, "null game");
   eg_solve_opts o{};
@@ -387,32 +421,69 @@ int eg_solve_ex(eg_game* g, const eg_solve_opts* opts, int64_t* credits, eg_stat
   HIPCHK(hipSetDevice(ctx->cfg.device));
   hipStream_t s = ctx->stream;
   const eg::DevGame& dg = g->dg;
+  const int grid = g->grid;
   const double t0 = now_s();
+  const uint64_t dense_at = std::max<uint64_t>(1, (uint64_t)g->n / 32);  // active vertices
   HIPCHK(hipMemsetAsync(dg.ctrl, 0, 4 * eg::C_WORDS, s));
-  HIPCHK(hipMemsetAsync(dg.stats, 0, 8 * eg::S_WORDS, s));
+  HIPCHK(hipMemsetAsync(dg.slots, 0, 8 * eg::S_WORDS * (size_t)grid, s));
   HIPCHK(hipEventRecord(g->ev[0], s));
-  HIPCHK(eg::launch_init(dg, g->vbits, g->h, o.resume ? 1 : 0, s));
+  HIPCHK(eg::launch_init(dg, g->vbits, o.resume ? 1 : 0, grid, s));
+  HIPCHK(hipMemcpyAsync(g->h_blk, dg.blk_chg, 4 * (size_t)grid, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  uint64_t active = 0;
+  for (int b = 0; b < grid; b++) active += g->h_blk[b];
   uint32_t r = 1;
   uint64_t launched = 0;
-  uint32_t batch = 2;
   int status = EG_OK;
-  for (;;) {
+  bool dense = active >= dense_at;
+  if (active && !dense) HIPCHK(eg::launch_compact(dg, 1, grid, s));
+  uint32_t batch = 2;
+  double t_kernels = 0;  // device time of the round kernels (back to back within a batch)
+  uint64_t dense_rounds = 0;
+  while (active) {
     uint32_t k = batch;
     if (max_rounds && launched + k > max_rounds) k = (uint32_t)(max_rounds - launched);
-    for (uint32_t j = 0; j < k; j++) HIPCHK(eg::launch_round(dg, g->vbits, g->h, r++, ctx->grid, s));
+    HIPCHK(hipEventRecord(g->ev[3], s));
+    for (uint32_t j = 0; j < k; j++) HIPCHK(eg::launch_round(dg, g->vbits, g->h, dense, r++, grid, s));
+    HIPCHK(hipEventRecord(g->ev[4], s));
     launched += k;
+    dense_rounds += dense ? k : 0;
     HIPCHK(hipMemcpyAsync(g->h_ctrl, dg.ctrl, 4 * eg::C_WORDS, hipMemcpyDeviceToHost, s));
+    if (dense) HIPCHK(hipMemcpyAsync(g->h_blk, dg.blk_chg, 4 * (size_t)grid, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    if (g->h_ctrl[eg::C_CNT0 + r % 3] == 0) break;  // empty active set: fixpoint
-    if ((max_rounds && launched >= max_rounds) || (budget > 0 && now_s() - t0 > budget) ||
-        r > 0xFFFFFF00u) {
+    {
+      float ms = 0;
+      hipEventElapsedTime(&ms, g->ev[3], g->ev[4]);
+      t_kernels += ms * 1e-3;
+    }
+    bool next_dense = dense;
+    if (dense) {
+      if (g->h_ctrl[eg::C_ANY0 + (r - 1) % 3] == 0) break;  // nothing rose in the last round
+      uint64_t changed = 0;
+      for (int b = 0; b < grid; b++) changed += g->h_blk[b];
+      // predecessors of the changed vertices, at most
+      if ((double)changed * g->avg_indeg < (double)dense_at / 4) next_dense = false;
+    } else {
+      const uint64_t next = g->h_ctrl[eg::C_CNT0 + r % 3];
+      if (next == 0) break;
+      if (next >= dense_at) next_dense = true;
+    }
+    if ((max_rounds && launched >= max_rounds) || (budget > 0 && now_s() - t0 > budget) || r > 0xFFFFFF00u) {
       status = EG_ETIMEDOUT;
       break;
     }
-    if (batch < 64) batch *= 2;
+    if (next_dense != dense) {
+      if (!next_dense) HIPCHK(eg::launch_compact(dg, r, grid, s));
+      dense = next_dense;
+      batch = 2;
+    } else if (batch < 64) {
+      batch *= 2;
+    }
   }
   HIPCHK(hipEventRecord(g->ev[1], s));
+  HIPCHK(eg::launch_reduce_stats(dg, grid, s));
   HIPCHK(hipMemcpyAsync(g->h_stats, dg.stats, 8 * eg::S_WORDS, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(g->h_ctrl, dg.ctrl, 4 * eg::C_WORDS, hipMemcpyDeviceToHost, s));
   if (credits) {
     HIPCHK(eg::launch_output(dg, g->vbits, g->out64, s));
     HIPCHK(hipMemcpyAsync(credits, g->out64, 8 * (size_t)g->n, hipMemcpyDeviceToHost, s));
@@ -426,6 +497,7 @@ int eg_solve_ex(eg_game* g, const eg_solve_opts* opts, int64_t* credits, eg_stat
     st->relaxed_edges = g->h_stats[eg::S_EDGES];
     st->pushes = g->h_stats[eg::S_PUSHES];
     st->changes = g->h_stats[eg::S_CHANGES];
+    st->scanned_preds = g->h_stats[eg::S_SCANNED];
     float ms = 0;
     hipEventElapsedTime(&ms, g->ev[0], g->ev[1]);
     st->t_solve = ms * 1e-3;
@@ -433,11 +505,15 @@ int eg_solve_ex(eg_game* g, const eg_solve_opts* opts, int64_t* credits, eg_stat
     st->t_d2h = ms * 1e-3;
     const double vb = g->vbits / 8;
     // algorithmic bytes: per relaxed edge the {target, weight} pair and f(target);
-    // per lift the list entry, the two row starts and f(v); per change the store
-    // of f(v) and the two predecessor-list starts; per push the list entry
-    st->model_bytes = st->relaxed_edges * (8 + vb) + st->lifts * (4 + 8 + vb) +
-                      st->changes * (vb + 8) + st->pushes * 4.0;
+    // per lift the active-set entry, the two row starts and f(v); per change the
+    // store of f(v) and the two predecessor-list starts; per scanned predecessor
+    // its id and its flag; per push the new entry
+    st->model_bytes = st->relaxed_edges * (8 + vb) + st->lifts * (4 + 8 + vb) + st->changes * (vb + 8) +
+                      st->scanned_preds * 8.0 + st->pushes * 4.0;
     st->achieved_gbps = st->t_solve > 0 ? st->model_bytes / st->t_solve / 1e9 : 0;
+    st->t_round_kernels = t_kernels;
+    st->launched_rounds = launched;
+    st->dense_rounds = dense_rounds;
   }
   if (status != EG_OK) return fail(status, "budget exhausted after %llu rounds", (unsigned long long)launched);
   return EG_OK;

@@ -11,15 +11,15 @@ namespace eg {
 constexpr uint32_t OWNER_BIT = 0x80000000u;
 constexpr uint32_t ROW_MASK = 0x7FFFFFFFu;
 
-// ctrl[] words (uint32) and stats[] words (uint64) in device memory
+// ctrl[] words (uint32) in device memory
 enum Ctrl : int {
-  C_CNT0 = 0,      // C_CNT0 + (r % 3): size of the active list of round r
-  C_ROUNDS = 3,    // rounds with a non-empty active set
-  C_DONE = 4,      // dense driver: blocks finished in the current round
-  C_MODE = 5,      // dense driver: representation of the next round
+  C_CNT0 = 0,    // C_CNT0 + (r % 3): length of the active list of round r (sparse rounds)
+  C_ANY0 = 3,    // C_ANY0 + (r % 3): nonzero if some value rose in round r (round 0 = init)
+  C_ROUNDS = 6,  // rounds with a non-empty active set
   C_WORDS = 8
 };
-enum Stat : int { S_LIFTS = 0, S_EDGES = 1, S_PUSHES = 2, S_CHANGES = 3, S_WORDS = 4 };
+// counters per block (slots) and totals (stats), uint64
+enum Stat : int { S_LIFTS = 0, S_EDGES = 1, S_PUSHES = 2, S_CHANGES = 3, S_SCANNED = 4, S_WORDS = 5 };
 
 // Everything a kernel needs to see of one game (passed by value).
 struct DevGame {
@@ -30,11 +30,15 @@ struct DevGame {
   const uint32_t* rev_off;  // n+1 predecessor-list starts (the paper's CSC)
   const int32_t* rev_src;   // m predecessor ids, one per edge
   void* f;                  // n values, int32 or int64 (vbits)
-  uint32_t* stamp;          // n: stamp[v] == r  <=>  v is active in round r
+  uint8_t* act0;            // n (padded to 4): flags of the active set of even rounds
+  uint8_t* act1;            // n (padded to 4): flags of the active set of odd rounds
   int32_t* wl0;             // n: active list of even rounds
   int32_t* wl1;             // n: active list of odd rounds
+  const uint32_t* act_bits; // ceil(n/32): initially active vertices (Alg. 3 line 3)
   uint32_t* ctrl;           // C_WORDS
-  unsigned long long* stats;  // S_WORDS
+  uint32_t* blk_chg;        // per block: values raised in its last round (init: vertices activated)
+  unsigned long long* slots;  // per block: S_WORDS counters accumulated over the solve
+  unsigned long long* stats;  // S_WORDS totals
   int64_t bound;            // B
   int64_t top;              // device encoding of TOP: B + P + 1, P = largest stored weight
 };
@@ -49,8 +53,11 @@ hipError_t launch_reverse_csr(const uint32_t* rs, const int2* edges, int32_t n, 
 size_t scan_tmp_words(size_t count);
 
 // Solve steps
-hipError_t launch_init(const DevGame& g, int vbits, int h, int resume, hipStream_t s);
-hipError_t launch_round(const DevGame& g, int vbits, int h, uint32_t r, int grid, hipStream_t s);
+constexpr int TILE_VERTICES = 256;  // vertices (or list entries) per block tile
+hipError_t launch_init(const DevGame& g, int vbits, int resume, int grid, hipStream_t s);
+hipError_t launch_compact(const DevGame& g, uint32_t r, int grid, hipStream_t s);
+hipError_t launch_round(const DevGame& g, int vbits, int h, bool dense, uint32_t r, int grid, hipStream_t s);
+hipError_t launch_reduce_stats(const DevGame& g, int nblocks, hipStream_t s);
 hipError_t launch_output(const DevGame& g, int vbits, int64_t* out, hipStream_t s);
 hipError_t launch_input(const DevGame& g, int vbits, const int64_t* in, hipStream_t s);
 

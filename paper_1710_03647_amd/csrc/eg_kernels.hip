@@ -150,15 +150,15 @@ __device__ __forceinline__ int32_t source_of(const uint32_t* rs, int32_t n, uint
   return lo;
 }
 
-// Each thread walks edges e = first, first + stride, ...; its source index only
-// moves forward, so after one binary search it advances by scanning.
+// Each thread takes a contiguous run of edges: one binary search finds the
+// source of its first edge, after which the source only moves forward.
 __global__ void k_scatter_preds(const uint32_t* rs, const int2* edges, int32_t n, uint32_t m,
-                                uint32_t* cursor, int32_t* rev_src) {
-  const uint32_t stride = gridDim.x * blockDim.x;
-  uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= m) return;
-  int32_t v = source_of(rs, n, e);
-  for (; e < m; e += stride) {
+                                uint32_t chunk, uint32_t* cursor, int32_t* rev_src) {
+  const uint64_t first = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * chunk;
+  if (first >= m) return;
+  const uint32_t last = (uint32_t)std::min<uint64_t>(m, first + chunk);
+  int32_t v = source_of(rs, n, (uint32_t)first);
+  for (uint32_t e = (uint32_t)first; e < last; e++) {
     while ((rs[v + 1] & ROW_MASK) <= e) v++;
     const uint32_t slot = atomicAdd(&cursor[edges[e].x], 1u);
     rev_src[slot] = v;
@@ -177,127 +177,343 @@ hipError_t launch_reverse_csr(const uint32_t* rs, const int2* edges, int32_t n, 
   if (e != hipSuccess) return e;
   e = hipMemcpyAsync(cursor, rev_off, sizeof(uint32_t) * (size_t)n, hipMemcpyDeviceToDevice, s);
   if (e != hipSuccess) return e;
-  if (m > 0)
-    hipLaunchKernelGGL(k_scatter_preds, dim3(grid_e), dim3(BLOCK), 0, s, rs, edges, n, m, cursor,
+  if (m > 0) {
+    const uint32_t chunk = 16;
+    const int grid_s = (int)(((uint64_t)m + (uint64_t)chunk * BLOCK - 1) / ((uint64_t)chunk * BLOCK));
+    hipLaunchKernelGGL(k_scatter_preds, dim3(grid_s), dim3(BLOCK), 0, s, rs, edges, n, m, chunk, cursor,
                        rev_src);
+  }
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- solve
-// Initial active set of Alg. 3 (and Alg. 1): player-0 vertices whose out-edges
-// all have negative weight, player-1 vertices with some negative out-edge.
-// Equivalently, the vertices whose lift from f = 0 is positive.  With resume,
-// f is kept and every vertex is active.
-template <int H, typename V>
-__global__ __launch_bounds__(BLOCK) void k_init(DevGame g, int resume) {
-  V* f = (V*)g.f;
-  const uint32_t sub = threadIdx.x & (H - 1);
-  const uint32_t group = (blockIdx.x * blockDim.x + threadIdx.x) / H;
-  const uint32_t ngroups = gridDim.x * blockDim.x / H;
-  uint32_t* count = &g.ctrl[C_CNT0 + 1];
-  for (uint32_t v = group; v < (uint32_t)g.n; v += ngroups) {
-    bool active = true;
-    if (!resume) {
-      const uint32_t a = g.rs[v], b = g.rs[v + 1];
-      const bool p1 = (a & OWNER_BIT) != 0;
-      int any_neg = 0, all_neg = 1;
-      for (uint32_t e = (a & ROW_MASK) + sub; e < (b & ROW_MASK); e += H) {
-        const int neg = g.edges[e].y < 0;
-        any_neg |= neg;
-        all_neg &= neg;
-      }
+//
+// Active sets.  Byte flags act[r & 1][v] != 0 mark v as a member of the active
+// set L_r of round r (Alg. 3); round r clears the flags it consumes and sets
+// flags in act[(r+1) & 1] for L_{r+1}, so the two sets never interfere.  A
+// round runs in one of two representations:
+//   sparse: L_r is also a list (wl[r & 1], length ctrl[C_CNT0 + r % 3]); a
+//           predecessor p joins L_{r+1} through an atomic OR on the word that
+//           holds its flag (the old value tells whether it was already in),
+//           is staged in LDS, and one global atomic per block appends the
+//           block's entries;
+//   dense:  only the flags; each block sweeps tiles of V and a predecessor
+//           joins L_{r+1} by a plain byte store (every writer stores the same
+//           value, so no atomic is needed).
+// The flag arrays are n bytes each, small enough to stay in L2.
+//
+// Per round each block writes its own counters (stats slots, changes), so no
+// counter is shared between blocks except the list length of sparse rounds.
+
+constexpr int TILE = TILE_VERTICES;  // list entries / vertices per tile
+static_assert(TILE == BLOCK, "one tile entry per thread");
+constexpr int UNROLL = 8;           // edges (or predecessor entries) per thread in flight
+constexpr int PUSH_CAP = 2048;      // staged list entries per block (sparse rounds)
+
+// Append `item` for the lanes with want = true to an LDS array: one LDS atomic per wave.
+__device__ __forceinline__ void lds_append(bool want, int32_t item, int32_t* buf, uint32_t* count) {
+  const unsigned long long m = __ballot(want);
+  if (m == 0) return;
+  const uint32_t leader = __ffsll((long long)m) - 1;
+  uint32_t base = 0;
+  if (lane_id() == leader) base = atomicAdd(count, (uint32_t)__popcll(m));
+  base = __shfl(base, leader, WAVE);
+  if (want) buf[base + mbcnt(m)] = item;
+}
+
+// Exclusive scan over the BLOCK threads; *total receives the sum.  Contains a
+// barrier; wsum (BLOCK/WAVE words of LDS) may be reused after the next barrier.
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t* wsum, uint32_t* total) {
+  const uint32_t lane = lane_id(), wid = threadIdx.x / WAVE;
+  uint32_t incl = x;
 #pragma unroll
-      for (int o = H / 2; o > 0; o >>= 1) {
-        any_neg |= __shfl_xor(any_neg, o, H);
-        all_neg &= __shfl_xor(all_neg, o, H);
-      }
-      active = p1 ? any_neg != 0 : all_neg != 0;
+  for (int o = 1; o < WAVE; o <<= 1) {
+    const uint32_t y = __shfl_up(incl, o, WAVE);
+    if (lane >= (uint32_t)o) incl += y;
+  }
+  if (lane == WAVE - 1) wsum[wid] = incl;
+  __syncthreads();
+  uint32_t off = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < BLOCK / WAVE; w++) {
+    const uint32_t sw = wsum[w];
+    off += (uint32_t)w < wid ? sw : 0u;
+    tot += sw;
+  }
+  *total = tot;
+  return off + incl - x;
+}
+
+// Largest i in [0, BLOCK) with pre[i] <= x, given pre[0] = 0 <= x < pre[BLOCK]:
+// the thread whose (non-empty) range [pre[i], pre[i+1]) holds x.
+__device__ __forceinline__ uint32_t find_range(const uint32_t* pre, uint32_t x) {
+  uint32_t lo = 0, hi = BLOCK;
+#pragma unroll
+  for (int step = 0; step < 8; step++) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (pre[mid] <= x) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+template <typename V>
+struct RoundShared {
+  uint32_t epre[BLOCK + 1];  // exclusive prefix of out-degrees of the tile's active vertices
+  uint32_t ebeg[BLOCK];      // their row starts with the owner bit
+  V key[BLOCK];              // running min of the per-edge keys (negated terms for player 1)
+  uint32_t ppre[BLOCK + 1];  // exclusive prefix of in-degrees of the tile's changed vertices
+  uint32_t pbeg[BLOCK];      // their predecessor-list starts
+  uint32_t wsum[BLOCK / WAVE];
+  int32_t push[PUSH_CAP];    // sparse: staged entries of L_{r+1}
+  unsigned long long st[S_WORDS];
+  uint32_t n_push, base;
+};
+
+// Reads of data used once per round (plain loads measured faster than
+// non-temporal ones on gfx950 here).
+__device__ __forceinline__ int2 load_edge(const int2* edges, uint32_t e) { return edges[e]; }
+template <typename T>
+__device__ __forceinline__ T load_stream(const T* p) {
+  return *p;
+}
+
+// Lanes with want = true activate p for L_{r+1} (flag array act_next).
+template <bool DENSE, typename V>
+__device__ __forceinline__ void activate(const DevGame& g, RoundShared<V>& sh, bool want, int32_t p,
+                                         uint8_t* act_next, int32_t* wl_out, uint32_t* cnt_out,
+                                         unsigned long long& pushes) {
+  if (DENSE) {
+    if (want) act_next[p] = 1;  // every writer stores the same value
+  } else {
+    bool ins = false;
+    if (want && act_next[p] == 0) {
+      const uint32_t bit = 1u << (8 * (p & 3));
+      ins = (atomicOr((uint32_t*)(act_next + (p & ~3)), bit) & bit) == 0;
     }
-    if (sub == 0) {
-      if (!resume) f[v] = 0;
-      g.stamp[v] = active ? 1u : 0u;
+    pushes += ins;
+    const unsigned long long m = __ballot(ins);
+    if (m == 0) return;
+    const uint32_t leader = __ffsll((long long)m) - 1;
+    uint32_t base = 0;
+    if (lane_id() == leader) base = atomicAdd(&sh.n_push, (uint32_t)__popcll(m));
+    base = __shfl(base, leader, WAVE);
+    if (ins) {
+      const uint32_t slot = base + mbcnt(m);
+      if (slot < (uint32_t)PUSH_CAP) sh.push[slot] = p;
+      else wl_out[atomicAdd(cnt_out, 1u)] = p;  // stage full: append directly
     }
-    wave_append(sub == 0 && active, (int32_t)v, g.wl1, count);
   }
 }
 
-// One round of Alg. 3 over the active list of round r, fused: each group of H
-// lanes lifts one vertex v (Def. 6) from a coalesced read of its out-edges and
-// a gather of f at the targets, combines the lanes by shuffles, stores f(v) in
-// place if it rose, and then scans pre(v) to activate every predecessor for
-// round r+1 exactly once (stamp test-and-set, wave-aggregated append).
-template <int H, typename V>
-__global__ __launch_bounds__(BLOCK) void k_round(DevGame g, uint32_t r) {
-  __shared__ unsigned long long s_stats[S_WORDS];
-  if (threadIdx.x < S_WORDS) s_stats[threadIdx.x] = 0;
-  const uint32_t n_in = g.ctrl[C_CNT0 + r % 3];
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    g.ctrl[C_CNT0 + (r + 2) % 3] = 0;  // the list of round r-1, recycled for round r+2
-    if (n_in) g.ctrl[C_ROUNDS] += 1;
-  }
+// Build L_1: f = 0 (kept on resume) and the round-1 flag on the initially active
+// vertices, whose flags were derived from the weights when the game was
+// created (player 0: every out-edge negative; player 1: some out-edge
+// negative; Alg. 3 line 3); with resume every vertex is active.  Each block
+// records how many it activated.
+template <typename V>
+__global__ __launch_bounds__(BLOCK) void k_init(DevGame g, int resume) {
+  __shared__ uint32_t s_cnt;
+  if (threadIdx.x == 0) s_cnt = 0;
   __syncthreads();
-  if (n_in == 0) return;
-
   V* f = (V*)g.f;
+  uint32_t mine = 0;
+  for (uint32_t v = blockIdx.x * BLOCK + threadIdx.x; v < (uint32_t)g.n; v += gridDim.x * BLOCK) {
+    const bool act = resume || ((g.act_bits[v >> 5] >> (v & 31)) & 1u);
+    if (!resume) f[v] = 0;
+    g.act0[v] = 0;
+    g.act1[v] = act ? 1 : 0;
+    mine += act;
+  }
+  atomicAdd(&s_cnt, mine);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    g.blk_chg[blockIdx.x] = s_cnt;
+    if (s_cnt) g.ctrl[C_ANY0 + 0] = 1;
+  }
+}
+
+// L_r as a list from its flags (used when a dense round is followed by sparse ones).
+__global__ __launch_bounds__(BLOCK) void k_compact(DevGame g, uint32_t r) {
+  __shared__ int32_t buf[PUSH_CAP];
+  __shared__ uint32_t nb, base;
+  int32_t* wl = (r & 1) ? g.wl1 : g.wl0;
+  uint32_t* cnt = &g.ctrl[C_CNT0 + r % 3];
+  if (threadIdx.x == 0) nb = 0;
+  __syncthreads();
+  const uint32_t ntiles = ((uint32_t)g.n + TILE - 1) / TILE;
+  for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const uint32_t v = t * TILE + threadIdx.x;
+    lds_append(v < (uint32_t)g.n && ((r & 1) ? g.act1 : g.act0)[v] != 0, (int32_t)v, buf, &nb);
+    __syncthreads();
+    if (nb > PUSH_CAP - TILE || t + gridDim.x >= ntiles) {
+      if (threadIdx.x == 0) base = nb ? atomicAdd(cnt, nb) : 0;
+      __syncthreads();
+      for (uint32_t i = threadIdx.x; i < nb; i += BLOCK) wl[base + i] = buf[i];
+      __syncthreads();
+      if (threadIdx.x == 0) nb = 0;
+    }
+    __syncthreads();
+  }
+}
+
+// One round of Alg. 3 over L_r.  Every active vertex is lifted in place
+// (chaotic updates are exact, see above) and the predecessors of every vertex
+// whose value rose form L_{r+1}.  A block takes a tile of TILE list entries
+// (sparse) or vertices (dense) and flattens the work: the out-edges of the
+// tile's active vertices are numbered by a block scan of their degrees, each
+// thread takes UNROLL edges at a stride of BLOCK (coalesced {target, weight}
+// reads, UNROLL gathers of f in flight) and folds its terms into the vertex's
+// LDS key with an atomic min (player 1 keys are negated terms, so one min
+// serves both players, Def. 6).  The predecessor lists of the changed
+// vertices are flattened the same way.  Any degree distribution is balanced
+// across the block.
+template <typename V, bool DENSE>
+__global__ __launch_bounds__(BLOCK) void k_round(DevGame g, uint32_t r) {
+  __shared__ RoundShared<V> sh;
+  const uint32_t tid = threadIdx.x;
+  uint32_t items;
+  if (DENSE) items = g.ctrl[C_ANY0 + (r - 1) % 3] ? (uint32_t)g.n : 0u;
+  else items = g.ctrl[C_CNT0 + r % 3];
+  if (blockIdx.x == 0 && tid == 0) {
+    g.ctrl[C_CNT0 + (r + 2) % 3] = 0;  // recycled for round r+2
+    g.ctrl[C_ANY0 + (r + 1) % 3] = 0;  // written by round r+1
+    if (items) g.ctrl[C_ROUNDS] += 1;
+  }
+  if (items == 0) {
+    if (tid == 0) g.blk_chg[blockIdx.x] = 0;
+    return;
+  }
+  if (tid == 0) sh.n_push = 0;
+  if (tid < S_WORDS) sh.st[tid] = 0;
+  V* f = (V*)g.f;
+  const V bound = (V)g.bound, top = (V)g.top;
+  uint8_t* act_cur = (r & 1) ? g.act1 : g.act0;
+  uint8_t* act_next = (r & 1) ? g.act0 : g.act1;
   const int32_t* wl_in = (r & 1) ? g.wl1 : g.wl0;
   int32_t* wl_out = (r & 1) ? g.wl0 : g.wl1;
   uint32_t* cnt_out = &g.ctrl[C_CNT0 + (r + 1) % 3];
-  const uint32_t next = r + 1;
-  const V bound = (V)g.bound, top = (V)g.top;
+  unsigned long long lifts = 0, edges_read = 0, changes = 0, pushes = 0, scanned = 0;
+  const uint32_t ntiles = (items + TILE - 1) / TILE;
 
-  const uint32_t sub = threadIdx.x & (H - 1);
-  const uint32_t leader = lane_id() & ~(uint32_t)(H - 1);
-  const uint32_t group = (blockIdx.x * blockDim.x + threadIdx.x) / H;
-  const uint32_t ngroups = gridDim.x * blockDim.x / H;
-  unsigned long long lifts = 0, edges_read = 0, changes = 0, pushes = 0;
-
-  for (uint32_t i = group; i < n_in; i += ngroups) {
-    const int32_t v = wl_in[i];
-    const uint32_t a = g.rs[v], b = g.rs[v + 1];
-    const uint32_t beg = a & ROW_MASK, end = b & ROW_MASK;
-    const bool p1 = (a & OWNER_BIT) != 0;
-    V acc = p1 ? V(0) : std::numeric_limits<V>::max();
-    for (uint32_t e = beg + sub; e < end; e += H) {
-      const int2 ed = g.edges[e];
-      V t = f[ed.x] - (V)ed.y;
-      t = t > V(0) ? t : V(0);
-      acc = p1 ? (t > acc ? t : acc) : (t < acc ? t : acc);
+  for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    __syncthreads();  // the previous tile is done with the shared arrays
+    const uint32_t idx = t * TILE + tid;
+    int32_t v = -1;
+    if (idx < items) {
+      if (DENSE) v = act_cur[idx] ? (int32_t)idx : -1;
+      else v = wl_in[idx];
     }
+    uint32_t raw = 0, deg = 0, pb = 0, pe = 0;
+    V old = 0;
+    if (v >= 0) {
+      act_cur[v] = 0;  // consumed
+      raw = load_stream(g.rs + v);
+      deg = (load_stream(g.rs + v + 1) & ROW_MASK) - (raw & ROW_MASK);
+      old = f[v];
+      pb = load_stream(g.rev_off + v);
+      pe = load_stream(g.rev_off + v + 1);
+    }
+    uint32_t E;
+    const uint32_t ex = block_excl_scan(deg, sh.wsum, &E);
+    sh.epre[tid] = ex;
+    if (tid == BLOCK - 1) sh.epre[BLOCK] = E;
+    sh.ebeg[tid] = raw;
+    sh.key[tid] = (raw & OWNER_BIT) ? V(0) : std::numeric_limits<V>::max();
+    __syncthreads();
+    if (E == 0) continue;  // block-uniform: no active vertex in this tile
+
+    for (uint32_t x0 = 0; x0 < E; x0 += BLOCK * UNROLL) {
+      uint32_t slot[UNROLL];
+      int2 ed[UNROLL];
+      V fu[UNROLL];
 #pragma unroll
-    for (int o = H / 2; o > 0; o >>= 1) {
-      const V other = __shfl_xor(acc, o, H);
-      acc = p1 ? (other > acc ? other : acc) : (other < acc ? other : acc);
+      for (int j = 0; j < UNROLL; j++) {
+        const uint32_t x = x0 + j * BLOCK + tid;
+        slot[j] = BLOCK;
+        if (x < E) {
+          const uint32_t s = find_range(sh.epre, x);
+          slot[j] = s;
+          ed[j] = load_edge(g.edges, (sh.ebeg[s] & ROW_MASK) + (x - sh.epre[s]));
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < UNROLL; j++)
+        if (slot[j] < BLOCK) fu[j] = f[ed[j].x];
+#pragma unroll
+      for (int j = 0; j < UNROLL; j++)
+        if (slot[j] < BLOCK) {
+          V tm = fu[j] - (V)ed[j].y;
+          tm = tm > V(0) ? tm : V(0);
+          __hip_atomic_fetch_min(&sh.key[slot[j]], (sh.ebeg[slot[j]] & OWNER_BIT) ? -tm : tm,
+                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
     }
-    if (acc > bound) acc = top;
-    int changed = 0;
-    if (sub == 0) {
-      const V old = f[v];
+    __syncthreads();
+
+    uint32_t ideg = 0;
+    if (v >= 0) {
+      const V k = sh.key[tid];
+      V nv = (raw & OWNER_BIT) ? -k : k;
+      if (nv > bound) nv = top;
       lifts++;
-      edges_read += end - beg;
-      if (acc != old) {
-        f[v] = acc;
-        changed = 1;
+      edges_read += deg;
+      if (nv != old) {
+        f[v] = nv;
         changes++;
+        ideg = pe - pb;
       }
     }
-    changed = __shfl(changed, leader, WAVE);
-    if (changed) {
-      const uint32_t pb = g.rev_off[v], pe = g.rev_off[v + 1];
-      for (uint32_t k = pb + sub; k < pe; k += H) {
-        const int32_t p = g.rev_src[k];
-        bool want = false;
-        if (g.stamp[p] != next) want = atomicExch(&g.stamp[p], next) != next;
-        pushes += want;
-        wave_append(want, p, wl_out, cnt_out);
+    uint32_t P;
+    const uint32_t pex = block_excl_scan(ideg, sh.wsum, &P);
+    sh.ppre[tid] = pex;
+    if (tid == BLOCK - 1) sh.ppre[BLOCK] = P;
+    sh.pbeg[tid] = pb;
+    scanned += ideg;
+    __syncthreads();
+    for (uint32_t x0 = 0; x0 < P; x0 += BLOCK * UNROLL) {
+      int32_t pr[UNROLL];
+#pragma unroll
+      for (int j = 0; j < UNROLL; j++) {
+        const uint32_t x = x0 + j * BLOCK + tid;
+        pr[j] = -1;
+        if (x < P) {
+          const uint32_t s = find_range(sh.ppre, x);
+          pr[j] = load_stream(g.rev_src + sh.pbeg[s] + (x - sh.ppre[s]));
+        }
       }
+#pragma unroll
+      for (int j = 0; j < UNROLL; j++) activate<DENSE>(g, sh, pr[j] >= 0, pr[j], act_next, wl_out, cnt_out, pushes);
     }
   }
-  atomicAdd(&s_stats[S_LIFTS], lifts);
-  atomicAdd(&s_stats[S_EDGES], edges_read);
-  atomicAdd(&s_stats[S_CHANGES], changes);
-  atomicAdd(&s_stats[S_PUSHES], pushes);
+  atomicAdd(&sh.st[S_LIFTS], lifts);
+  atomicAdd(&sh.st[S_EDGES], edges_read);
+  atomicAdd(&sh.st[S_CHANGES], changes);
+  atomicAdd(&sh.st[S_PUSHES], pushes);
+  atomicAdd(&sh.st[S_SCANNED], scanned);
   __syncthreads();
-  if (threadIdx.x < S_WORDS && s_stats[threadIdx.x]) atomicAdd(&g.stats[threadIdx.x], s_stats[threadIdx.x]);
+  if (!DENSE) {
+    const uint32_t nf = sh.n_push < (uint32_t)PUSH_CAP ? sh.n_push : (uint32_t)PUSH_CAP;
+    if (tid == 0) sh.base = nf ? atomicAdd(cnt_out, nf) : 0u;
+    __syncthreads();
+    for (uint32_t i = tid; i < nf; i += BLOCK) wl_out[sh.base + i] = sh.push[i];
+  }
+  if (tid < S_WORDS) g.slots[blockIdx.x * S_WORDS + tid] += sh.st[tid];
+  if (tid == 0) {
+    g.blk_chg[blockIdx.x] = (uint32_t)sh.st[S_CHANGES];
+    if (sh.st[S_CHANGES]) g.ctrl[C_ANY0 + r % 3] = 1;
+  }
+}
+
+// stats[k] = sum over blocks of slots[b][k]
+__global__ void k_reduce_slots(DevGame g, uint32_t nblocks) {
+  __shared__ unsigned long long acc[S_WORDS];
+  if (threadIdx.x < S_WORDS) acc[threadIdx.x] = 0;
+  __syncthreads();
+  for (uint32_t b = threadIdx.x; b < nblocks; b += blockDim.x)
+    for (int k = 0; k < S_WORDS; k++) atomicAdd(&acc[k], g.slots[b * S_WORDS + k]);
+  __syncthreads();
+  if (threadIdx.x < S_WORDS) g.stats[threadIdx.x] = acc[threadIdx.x];
 }
 
 template <typename V>
@@ -332,48 +548,47 @@ int round_grid(int device) {
   return cus * 8;
 }
 
-template <typename V>
-static hipError_t init_v(const DevGame& g, int h, int resume, hipStream_t s) {
-  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(((int64_t)g.n * h + BLOCK - 1) / BLOCK, 16384));
-  switch (h) {
-#define EG_CASE(H) \
-  case H: hipLaunchKernelGGL((k_init<H, V>), dim3(grid), dim3(BLOCK), 0, s, g, resume); break;
-    EG_CASE(1) EG_CASE(2) EG_CASE(4) EG_CASE(8) EG_CASE(16) EG_CASE(32) EG_CASE(64)
-#undef EG_CASE
-    default: return hipErrorInvalidValue;
+static int vertex_grid(const DevGame& g, int max_grid) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>(((int64_t)g.n + TILE - 1) / TILE, max_grid));
+}
+
+hipError_t launch_init(const DevGame& g, int vbits, int resume, int grid, hipStream_t s) {
+  if (vbits == 32) hipLaunchKernelGGL(k_init<int32_t>, dim3(grid), dim3(BLOCK), 0, s, g, resume);
+  else hipLaunchKernelGGL(k_init<int64_t>, dim3(grid), dim3(BLOCK), 0, s, g, resume);
+  return hipGetLastError();
+}
+
+hipError_t launch_compact(const DevGame& g, uint32_t r, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_compact, dim3(grid), dim3(BLOCK), 0, s, g, r);
+  return hipGetLastError();
+}
+
+hipError_t launch_round(const DevGame& g, int vbits, int h, bool dense, uint32_t r, int grid, hipStream_t s) {
+  (void)h;
+  if (vbits == 32) {
+    if (dense) hipLaunchKernelGGL((k_round<int32_t, true>), dim3(grid), dim3(BLOCK), 0, s, g, r);
+    else hipLaunchKernelGGL((k_round<int32_t, false>), dim3(grid), dim3(BLOCK), 0, s, g, r);
+  } else {
+    if (dense) hipLaunchKernelGGL((k_round<int64_t, true>), dim3(grid), dim3(BLOCK), 0, s, g, r);
+    else hipLaunchKernelGGL((k_round<int64_t, false>), dim3(grid), dim3(BLOCK), 0, s, g, r);
   }
   return hipGetLastError();
 }
 
-template <typename V>
-static hipError_t round_v(const DevGame& g, int h, uint32_t r, int grid, hipStream_t s) {
-  switch (h) {
-#define EG_CASE(H) \
-  case H: hipLaunchKernelGGL((k_round<H, V>), dim3(grid), dim3(BLOCK), 0, s, g, r); break;
-    EG_CASE(1) EG_CASE(2) EG_CASE(4) EG_CASE(8) EG_CASE(16) EG_CASE(32) EG_CASE(64)
-#undef EG_CASE
-    default: return hipErrorInvalidValue;
-  }
+hipError_t launch_reduce_stats(const DevGame& g, int nblocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_slots, dim3(1), dim3(1024), 0, s, g, (uint32_t)nblocks);
   return hipGetLastError();
-}
-
-hipError_t launch_init(const DevGame& g, int vbits, int h, int resume, hipStream_t s) {
-  return vbits == 32 ? init_v<int32_t>(g, h, resume, s) : init_v<int64_t>(g, h, resume, s);
-}
-
-hipError_t launch_round(const DevGame& g, int vbits, int h, uint32_t r, int grid, hipStream_t s) {
-  return vbits == 32 ? round_v<int32_t>(g, h, r, grid, s) : round_v<int64_t>(g, h, r, grid, s);
 }
 
 hipError_t launch_output(const DevGame& g, int vbits, int64_t* out, hipStream_t s) {
-  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(((int64_t)g.n + BLOCK - 1) / BLOCK, 8192));
+  const int grid = vertex_grid(g, 8192);
   if (vbits == 32) hipLaunchKernelGGL(k_output<int32_t>, dim3(grid), dim3(BLOCK), 0, s, g, out);
   else hipLaunchKernelGGL(k_output<int64_t>, dim3(grid), dim3(BLOCK), 0, s, g, out);
   return hipGetLastError();
 }
 
 hipError_t launch_input(const DevGame& g, int vbits, const int64_t* in, hipStream_t s) {
-  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(((int64_t)g.n + BLOCK - 1) / BLOCK, 8192));
+  const int grid = vertex_grid(g, 8192);
   if (vbits == 32) hipLaunchKernelGGL(k_input<int32_t>, dim3(grid), dim3(BLOCK), 0, s, g, in);
   else hipLaunchKernelGGL(k_input<int64_t>, dim3(grid), dim3(BLOCK), 0, s, g, in);
   return hipGetLastError();

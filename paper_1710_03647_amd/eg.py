@@ -52,9 +52,12 @@ class eg_game_desc(ctypes.Structure):
 class eg_stats(ctypes.Structure):
     _fields_ = [("rounds", ctypes.c_uint64), ("lifts", ctypes.c_uint64),
                 ("relaxed_edges", ctypes.c_uint64), ("pushes", ctypes.c_uint64),
-                ("changes", ctypes.c_uint64), ("t_upload", ctypes.c_double),
+                ("changes", ctypes.c_uint64), ("scanned_preds", ctypes.c_uint64),
+                ("t_upload", ctypes.c_double),
                 ("t_rcsr", ctypes.c_double), ("t_solve", ctypes.c_double), ("t_d2h", ctypes.c_double),
-                ("model_bytes", ctypes.c_double), ("achieved_gbps", ctypes.c_double)]
+                ("model_bytes", ctypes.c_double), ("achieved_gbps", ctypes.c_double),
+                ("t_round_kernels", ctypes.c_double), ("launched_rounds", ctypes.c_uint64),
+                ("dense_rounds", ctypes.c_uint64)]
 
     def to_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
