@@ -102,6 +102,8 @@ typedef struct {
   double model_bytes;     /* algorithmic bytes moved by the solve (see eg_solve_ex) */
   double achieved_gbps;   /* model_bytes / t_solve / 1e9 */
   double t_round_kernels; /* device time of the round kernels alone, seconds */
+  double t_queue;         /* eg_poll: submission to admission, seconds */
+  double t_latency;       /* eg_poll: submission to result, seconds */
   uint64_t launched_rounds; /* round kernels launched (empty ones after the fixpoint included) */
   uint64_t dense_rounds;  /* of which in the dense representation */
 } eg_stats;
@@ -176,6 +178,17 @@ int eg_set_measure(eg_game* g, const int64_t* f);
 int eg_submit(eg_ctx* ctx, const eg_game_desc* desc, eg_ticket* out);
 int eg_poll(eg_ctx* ctx, eg_ticket t, int64_t* credits, eg_stats* stats);
 int eg_cancel(eg_ctx* ctx, eg_ticket t);
+
+/* As eg_poll, but blocks until the ticket is finished or timeout_s seconds
+ * have passed (then EG_PENDING; timeout_s <= 0 waits without limit). */
+int eg_wait(eg_ctx* ctx, eg_ticket t, int64_t* credits, eg_stats* stats, double timeout_s);
+
+/* Batching: solve `count` games together in the batched device iteration
+ * (all resident games advance one round per launch, each retired at its own
+ * fixpoint) and block until all are done.  credits[i] receives game i's n
+ * credits; stats (nullable) count entries.  The games must fit the context's
+ * HBM budget one at a time; they are admitted as room frees up. */
+int eg_solve_batch(eg_ctx* ctx, const eg_game_desc* games, int count, int64_t* const* credits, eg_stats* stats);
 
 /* Message of the last failure on the calling thread ("" if none). */
 const char* eg_last_error(eg_ctx* ctx);

@@ -44,6 +44,7 @@ double now_s() {
 
 namespace eg {
 
+GameLayout plan_layout(int32_t n, int64_t m, int vbits, size_t nblk);
 void set_error(const char* msg) { t_err = msg; }
 const char* get_error() { return t_err.c_str(); }
 
@@ -52,7 +53,10 @@ int check_host(const eg_game_desc* d, int bound_mode, eg_game_info* info, std::s
                int64_t* clamp_out, std::vector<uint32_t>* act_bits) {
   auto bad = [&](const char* fmt, auto... a) {
     char buf[256];
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Wformat-security"
     snprintf(buf, sizeof buf, fmt, a...);
+#pragma clang diagnostic pop
     *why = buf;
     return EG_EINVAL;
   };
@@ -114,11 +118,7 @@ int check_host(const eg_game_desc* d, int bound_mode, eg_game_info* info, std::s
     info->value_bits = hi < ((__int128)1 << 31) ? 32 : 64;
     info->max_outdeg = max_out;
     info->max_indeg = max_in;
-    const size_t vb = info->value_bits / 8;
-    const size_t nn = (size_t)n, mm = (size_t)d->m;
-    info->device_bytes = align_up(4 * (nn + 1)) + align_up(8 * mm) + align_up(4 * (nn + 1)) +
-                         align_up(4 * mm) + align_up(vb * nn) + 3 * align_up(4 * nn) +
-                         align_up(8 * nn) + 2 * 256;
+    info->device_bytes = plan_layout(n, d->m, info->value_bits, 1).total;
   }
   return EG_OK;
 }
@@ -131,6 +131,7 @@ struct eg_ctx {
   bool own_stream = false;
   int grid = 2048;
   std::mutex solve_mu;
+  std::mutex server_mu;
   eg::Server* server = nullptr;
 };
 
@@ -155,7 +156,7 @@ struct eg_game {
   hipEvent_t ev[6] = {};
 };
 
-extern "C" {
+// The exported functions keep the C linkage of their declarations in eg.h.
 
 const char* eg_last_error(eg_ctx*) { return t_err.c_str(); }
 
@@ -202,118 +203,194 @@ int eg_ctx_create(const eg_config* cfg, eg_ctx** out) {
 
 int eg_ctx_destroy(eg_ctx* ctx) {
   if (!ctx) return fail(EG_EINVAL, "null context");
-  hipSetDevice(ctx->cfg.device);
+  (void)hipSetDevice(ctx->cfg.device);
   if (ctx->server) {
     eg::server_destroy(ctx->server);
     ctx->server = nullptr;
   }
-  if (ctx->own_stream) hipStreamDestroy(ctx->stream);
+  if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
   return EG_OK;
 }
 
 static void game_free(eg_game* g) {
   if (!g) return;
-  if (g->arena) hipFree(g->arena);
-  if (g->h_ctrl) hipHostFree(g->h_ctrl);
-  if (g->h_blk) hipHostFree(g->h_blk);
-  if (g->h_stats) hipHostFree(g->h_stats);
+  if (g->arena) (void)hipFree(g->arena);
+  if (g->h_ctrl) (void)hipHostFree(g->h_ctrl);
+  if (g->h_blk) (void)hipHostFree(g->h_blk);
+  if (g->h_stats) (void)hipHostFree(g->h_stats);
   for (auto& e : g->ev)
-    if (e) hipEventDestroy(e);
+    if (e) (void)hipEventDestroy(e);
   delete g;
 }
+
+// Host copy of a game given by device pointers (for validation).
+struct HostCopy {
+  std::vector<int64_t> off;
+  std::vector<int32_t> tgt, w;
+  std::vector<uint8_t> own;
+};
+
+static int host_view(const eg_game_desc* desc, hipStream_t s, HostCopy& hc, eg_game_desc& hd) {
+  hd = *desc;
+  if (desc->mem == EG_MEM_HOST) return EG_OK;
+  if (desc->mem != EG_MEM_DEVICE) return fail(EG_EINVAL, "unknown memory kind %d", desc->mem);
+  if (desc->n < 1 || desc->m < 0 || desc->m >= ((int64_t)1 << 31))
+    return fail(EG_EINVAL, "n = %d, m = %lld", desc->n, (long long)desc->m);
+  if (!desc->offsets || !desc->owner_bits || (desc->m > 0 && (!desc->targets || !desc->weights)))
+    return fail(EG_EINVAL, "null device pointer");
+  hc.off.resize((size_t)desc->n + 1);
+  hc.tgt.resize((size_t)desc->m);
+  hc.w.resize((size_t)desc->m);
+  hc.own.resize(((size_t)desc->n + 7) / 8);
+  HIPCHK(hipMemcpyAsync(hc.off.data(), desc->offsets, 8 * hc.off.size(), hipMemcpyDeviceToHost, s));
+  if (desc->m > 0) {
+    HIPCHK(hipMemcpyAsync(hc.tgt.data(), desc->targets, 4 * hc.tgt.size(), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(hc.w.data(), desc->weights, 4 * hc.w.size(), hipMemcpyDeviceToHost, s));
+  }
+  HIPCHK(hipMemcpyAsync(hc.own.data(), desc->owner_bits, hc.own.size(), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  hd.offsets = hc.off.data();
+  hd.targets = hc.tgt.data();
+  hd.weights = hc.w.data();
+  hd.owner_bits = hc.own.data();
+  hd.mem = EG_MEM_HOST;
+  return EG_OK;
+}
+
+namespace eg {
+
+GameLayout plan_layout(int32_t n, int64_t m, int vbits, size_t nblk) {
+  const size_t nn = (size_t)n, mm = (size_t)m, vb = (size_t)vbits / 8;
+  const size_t sizes[L_N] = {4 * (nn + 1), 8 * mm, 4 * (nn + 1), 4 * mm, vb * nn, 2 * align_up(nn + 4), 4 * nn,
+                             4 * nn, 8 * nn, 4 * C_WORDS, 8 * S_WORDS, 4 * ((nn + 31) / 32), 4 * nblk,
+                             8 * S_WORDS * nblk};
+  GameLayout L{};
+  for (int i = 0; i < L_N; i++) {
+    L.off[i] = L.total;
+    L.total += align_up(std::max<size_t>(sizes[i], 4));
+  }
+  return L;
+}
+
+void bind_layout(DevGame& dg, char* base, const GameLayout& L, int32_t n, int64_t m, int vbits) {
+  dg.n = n;
+  dg.m = (uint32_t)m;
+  dg.rs = (uint32_t*)(base + L.off[L_RS]);
+  dg.edges = (int2*)(base + L.off[L_EDGES]);
+  dg.rev_off = (uint32_t*)(base + L.off[L_ROFF]);
+  dg.rev_src = (int32_t*)(base + L.off[L_RSRC]);
+  dg.f = base + L.off[L_F];
+  dg.act0 = (uint8_t*)(base + L.off[L_ACT]);
+  dg.act1 = dg.act0 + align_up((size_t)n + 4);
+  dg.wl0 = (int32_t*)(base + L.off[L_WL0]);
+  dg.wl1 = (int32_t*)(base + L.off[L_WL1]);
+  dg.ctrl = (uint32_t*)(base + L.off[L_CTRL]);
+  dg.stats = (unsigned long long*)(base + L.off[L_STATS]);
+  dg.act_bits = (const uint32_t*)(base + L.off[L_ACTBITS]);
+  dg.blk_chg = (uint32_t*)(base + L.off[L_BLK]);
+  dg.slots = (unsigned long long*)(base + L.off[L_SLOTS]);
+  dg.vbits = vbits;
+}
+
+size_t staging_bytes(int32_t n, int64_t m, bool host_inputs) {
+  const size_t nn = (size_t)n, mm = (size_t)m;
+  size_t t = align_up(4 * (nn + 1)) + align_up(4 * scan_tmp_words(nn + 1));
+  if (host_inputs) t += align_up(8 * (nn + 1)) + 2 * align_up(std::max<size_t>(4 * mm, 4)) + align_up((nn + 7) / 8);
+  return t;
+}
+
+hipError_t upload_game(const eg_game_desc* d, const HostPrep& prep, DevGame& dg, void* staging, hipStream_t s,
+                       hipEvent_t after_layout) {
+  const size_t nn = (size_t)d->n, mm = (size_t)d->m;
+  const bool host_in = d->mem == EG_MEM_HOST;
+  char* sb = (char*)staging;
+  uint32_t* cursor = (uint32_t*)sb;
+  sb += align_up(4 * (nn + 1));
+  uint32_t* scan_tmp = (uint32_t*)sb;
+  const size_t scan_words = scan_tmp_words(nn + 1);
+  sb += align_up(4 * scan_words);
+  const int64_t* d_off = d->offsets;
+  const int32_t* d_tgt = d->targets;
+  const int32_t* d_w = d->weights;
+  const uint8_t* d_own = d->owner_bits;
+  hipError_t r;
+  if (host_in) {
+    int64_t* o = (int64_t*)sb;
+    sb += align_up(8 * (nn + 1));
+    int32_t* t = (int32_t*)sb;
+    sb += align_up(std::max<size_t>(4 * mm, 4));
+    int32_t* w = (int32_t*)sb;
+    sb += align_up(std::max<size_t>(4 * mm, 4));
+    uint8_t* ob = (uint8_t*)sb;
+    if ((r = hipMemcpyAsync(o, d->offsets, 8 * (nn + 1), hipMemcpyHostToDevice, s))) return r;
+    if (mm && (r = hipMemcpyAsync(t, d->targets, 4 * mm, hipMemcpyHostToDevice, s))) return r;
+    if (mm && (r = hipMemcpyAsync(w, d->weights, 4 * mm, hipMemcpyHostToDevice, s))) return r;
+    if ((r = hipMemcpyAsync(ob, d->owner_bits, (nn + 7) / 8, hipMemcpyHostToDevice, s))) return r;
+    d_off = o;
+    d_tgt = t;
+    d_w = w;
+    d_own = ob;
+  }
+  if ((r = hipMemcpyAsync((void*)dg.act_bits, prep.act_bits.data(), 4 * prep.act_bits.size(),
+                          hipMemcpyHostToDevice, s)))
+    return r;
+  if ((r = launch_layout(d_off, d_own, d_tgt, d_w, d->n, (uint32_t)mm, (int32_t)prep.clamp, (uint32_t*)dg.rs,
+                         (int2*)dg.edges, s)) != hipSuccess)
+    return r;
+  if (after_layout && (r = hipEventRecord(after_layout, s))) return r;
+  return launch_reverse_csr(dg.rs, dg.edges, d->n, (uint32_t)mm, (uint32_t*)dg.rev_off, (int32_t*)dg.rev_src,
+                            cursor, scan_tmp, scan_words, s);
+}
+
+int prepare(const eg_game_desc* desc, int bound_mode, hipStream_t s, HostPrep& prep, std::string* why) {
+  HostCopy hc;
+  eg_game_desc hd;
+  int rc = host_view(desc, s, hc, hd);
+  if (rc != EG_OK) {
+    *why = t_err;
+    return rc;
+  }
+  return check_host(&hd, bound_mode, &prep.info, why, &prep.clamp, &prep.act_bits);
+}
+
+}  // namespace eg
 
 int eg_create(eg_ctx* ctx, const eg_game_desc* desc, eg_game** out, eg_stats* st) {
   if (!ctx || !desc || !out) return fail(EG_EINVAL, "null argument");
   *out = nullptr;
   HIPCHK(hipSetDevice(ctx->cfg.device));
   hipStream_t s = ctx->stream;
-  // host view of the inputs for validation
-  eg_game_desc hd = *desc;
-  std::vector<int64_t> hoff;
-  std::vector<int32_t> htgt, hw;
-  std::vector<uint8_t> hown;
-  if (desc->mem == EG_MEM_DEVICE) {
-    if (desc->n < 1 || desc->m < 0) return fail(EG_EINVAL, "n = %d, m = %lld", desc->n, (long long)desc->m);
-    if (!desc->offsets || !desc->owner_bits || (desc->m > 0 && (!desc->targets || !desc->weights)))
-      return fail(EG_EINVAL, "null device pointer");
-    hoff.resize((size_t)desc->n + 1);
-    htgt.resize((size_t)desc->m);
-    hw.resize((size_t)desc->m);
-    hown.resize(((size_t)desc->n + 7) / 8);
-    HIPCHK(hipMemcpyAsync(hoff.data(), desc->offsets, 8 * hoff.size(), hipMemcpyDeviceToHost, s));
-    if (desc->m > 0) {
-      HIPCHK(hipMemcpyAsync(htgt.data(), desc->targets, 4 * htgt.size(), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipMemcpyAsync(hw.data(), desc->weights, 4 * hw.size(), hipMemcpyDeviceToHost, s));
-    }
-    HIPCHK(hipMemcpyAsync(hown.data(), desc->owner_bits, hown.size(), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    hd.offsets = hoff.data();
-    hd.targets = htgt.data();
-    hd.weights = hw.data();
-    hd.owner_bits = hown.data();
-    hd.mem = EG_MEM_HOST;
-  } else if (desc->mem != EG_MEM_HOST) {
-    return fail(EG_EINVAL, "unknown memory kind %d", desc->mem);
-  }
-  eg_game_info info{};
+  eg::HostPrep prep;
   std::string why;
-  int64_t clamp = 0;
-  std::vector<uint32_t> act_bits;
-  if (eg::check_host(&hd, ctx->cfg.bound_mode, &info, &why, &clamp, &act_bits) != EG_OK)
-    return fail(EG_EINVAL, "%s", why.c_str());
+  int rc = eg::prepare(desc, ctx->cfg.bound_mode, s, prep, &why);
+  if (rc != EG_OK) return fail(rc, "%s", why.c_str());
 
   eg_game* g = new eg_game();
   g->ctx = ctx;
   g->n = desc->n;
   g->m = desc->m;
   g->W = desc->W;
-  g->bound = info.bound;
-  g->vbits = info.value_bits;
-  g->info = info;
+  g->bound = prep.info.bound;
+  g->vbits = prep.info.value_bits;
+  g->info = prep.info;
   g->h = eg::pick_h((double)desc->m / desc->n);
-  const size_t nn = (size_t)g->n, mm = (size_t)g->m, vb = g->vbits / 8;
-  // one device allocation holds everything the game keeps
+  const size_t nn = (size_t)g->n;
   const size_t nblk = (size_t)std::max(1, std::min<int>(ctx->grid, (int)((nn + eg::TILE_VERTICES - 1) / eg::TILE_VERTICES)));
   g->grid = (int)nblk;
-  // one device allocation holds everything the game keeps
-  enum { A_RS, A_EDGES, A_ROFF, A_RSRC, A_F, A_STAMP, A_WL0, A_WL1, A_OUT, A_CTRL, A_STATS, A_ACT, A_BLK, A_SLOTS, A_N };
-  size_t offs[A_N], total = 0;
-  const size_t sizes[A_N] = {4 * (nn + 1), 8 * mm, 4 * (nn + 1), 4 * mm, vb * nn, 2 * align_up(nn + 4), 4 * nn, 4 * nn,
-                             8 * nn, 4 * eg::C_WORDS, 8 * eg::S_WORDS, 4 * act_bits.size(), 4 * nblk,
-                             8 * eg::S_WORDS * nblk};
-  for (int i = 0; i < A_N; i++) {
-    offs[i] = total;
-    total += align_up(std::max<size_t>(sizes[i], 4));
-  }
-  hipError_t e = hipMalloc(&g->arena, total);
+  const eg::GameLayout L = eg::plan_layout(g->n, g->m, g->vbits, nblk);
+  hipError_t e = hipMalloc(&g->arena, L.total);
   if (e != hipSuccess) {
     game_free(g);
-    return fail(EG_ENOMEM, "device allocation of %zu bytes failed: %s", total, hipGetErrorString(e));
+    return fail(EG_ENOMEM, "device allocation of %zu bytes failed: %s", L.total, hipGetErrorString(e));
   }
-  g->arena_bytes = total;
-  char* base = (char*)g->arena;
+  g->arena_bytes = L.total;
   eg::DevGame& dg = g->dg;
-  dg.n = g->n;
-  dg.m = (uint32_t)g->m;
-  dg.rs = (uint32_t*)(base + offs[A_RS]);
-  dg.edges = (int2*)(base + offs[A_EDGES]);
-  dg.rev_off = (uint32_t*)(base + offs[A_ROFF]);
-  dg.rev_src = (int32_t*)(base + offs[A_RSRC]);
-  dg.f = base + offs[A_F];
-  dg.act0 = (uint8_t*)(base + offs[A_STAMP]);
-  dg.act1 = dg.act0 + align_up(nn + 4);
-  dg.wl0 = (int32_t*)(base + offs[A_WL0]);
-  dg.wl1 = (int32_t*)(base + offs[A_WL1]);
-  g->out64 = (int64_t*)(base + offs[A_OUT]);
-  dg.ctrl = (uint32_t*)(base + offs[A_CTRL]);
-  dg.stats = (unsigned long long*)(base + offs[A_STATS]);
-  dg.act_bits = (const uint32_t*)(base + offs[A_ACT]);
-  dg.blk_chg = (uint32_t*)(base + offs[A_BLK]);
-  dg.slots = (unsigned long long*)(base + offs[A_SLOTS]);
+  eg::bind_layout(dg, (char*)g->arena, L, g->n, g->m, g->vbits);
+  g->out64 = (int64_t*)((char*)g->arena + L.off[eg::L_OUT]);
   dg.bound = g->bound;
-  dg.top = g->bound + clamp + 1;
-  g->avg_indeg = (double)mm / (double)nn;
+  dg.top = g->bound + prep.clamp + 1;
+  g->avg_indeg = (double)g->m / (double)nn;
 
   auto cleanup_fail = [&](int code, const char* what, hipError_t err) {
     game_free(g);
@@ -323,61 +400,30 @@ int eg_create(eg_ctx* ctx, const eg_game_desc* desc, eg_game** out, eg_stats* st
     return cleanup_fail(EG_EDEVICE, "hipHostMalloc", e);
   if ((e = hipHostMalloc((void**)&g->h_stats, 8 * eg::S_WORDS, hipHostMallocDefault)) != hipSuccess)
     return cleanup_fail(EG_EDEVICE, "hipHostMalloc", e);
-  for (auto& ev : g->ev)
-    if ((e = hipEventCreate(&ev)) != hipSuccess) return cleanup_fail(EG_EDEVICE, "hipEventCreate", e);
   if ((e = hipHostMalloc((void**)&g->h_blk, 4 * nblk, hipHostMallocDefault)) != hipSuccess)
     return cleanup_fail(EG_EDEVICE, "hipHostMalloc", e);
-  if ((e = hipMemcpyAsync((void*)dg.act_bits, act_bits.data(), 4 * act_bits.size(), hipMemcpyHostToDevice, s)) !=
-      hipSuccess)
-    return cleanup_fail(EG_EDEVICE, "upload of the initial active set", e);
+  for (auto& ev : g->ev)
+    if ((e = hipEventCreate(&ev)) != hipSuccess) return cleanup_fail(EG_EDEVICE, "hipEventCreate", e);
 
-  // staging for the raw inputs (host path) plus reverse-CSR scratch
-  const size_t scan_words = eg::scan_tmp_words(nn + 1);
-  const bool host_in = desc->mem == EG_MEM_HOST;
-  size_t so[6], stotal = 0;
-  const size_t ssz[6] = {host_in ? 8 * (nn + 1) : 0, host_in ? 4 * mm : 0, host_in ? 4 * mm : 0,
-                         host_in ? (nn + 7) / 8 : 0, 4 * (nn + 1), 4 * scan_words};
-  for (int i = 0; i < 6; i++) {
-    so[i] = stotal;
-    stotal += align_up(std::max<size_t>(ssz[i], 4));
-  }
   void* staging = nullptr;
-  if ((e = hipMalloc(&staging, stotal)) != hipSuccess) return cleanup_fail(EG_ENOMEM, "staging allocation", e);
-  char* sb = (char*)staging;
-  const int64_t* d_off = host_in ? (const int64_t*)(sb + so[0]) : desc->offsets;
-  const int32_t* d_tgt = host_in ? (const int32_t*)(sb + so[1]) : desc->targets;
-  const int32_t* d_w = host_in ? (const int32_t*)(sb + so[2]) : desc->weights;
-  const uint8_t* d_own = host_in ? (const uint8_t*)(sb + so[3]) : desc->owner_bits;
-  uint32_t* cursor = (uint32_t*)(sb + so[4]);
-  uint32_t* scan_tmp = (uint32_t*)(sb + so[5]);
-
+  if ((e = hipMalloc(&staging, eg::staging_bytes(g->n, g->m, desc->mem == EG_MEM_HOST))) != hipSuccess)
+    return cleanup_fail(EG_ENOMEM, "staging allocation", e);
   auto run = [&]() -> hipError_t {
     hipError_t r;
     if ((r = hipEventRecord(g->ev[0], s)) != hipSuccess) return r;
-    if (host_in) {
-      if ((r = hipMemcpyAsync((void*)d_off, desc->offsets, 8 * (nn + 1), hipMemcpyHostToDevice, s))) return r;
-      if (mm && (r = hipMemcpyAsync((void*)d_tgt, desc->targets, 4 * mm, hipMemcpyHostToDevice, s))) return r;
-      if (mm && (r = hipMemcpyAsync((void*)d_w, desc->weights, 4 * mm, hipMemcpyHostToDevice, s))) return r;
-      if ((r = hipMemcpyAsync((void*)d_own, desc->owner_bits, (nn + 7) / 8, hipMemcpyHostToDevice, s))) return r;
-    }
-    if ((r = eg::launch_layout(d_off, d_own, d_tgt, d_w, g->n, (uint32_t)mm, (int32_t)clamp,
-                               (uint32_t*)dg.rs, (int2*)dg.edges, s)) != hipSuccess) return r;
-    if ((r = hipEventRecord(g->ev[1], s)) != hipSuccess) return r;
-    if ((r = eg::launch_reverse_csr(dg.rs, dg.edges, g->n, (uint32_t)mm, (uint32_t*)dg.rev_off,
-                                    (int32_t*)dg.rev_src, cursor, scan_tmp, scan_words, s)) != hipSuccess)
-      return r;
+    if ((r = eg::upload_game(desc, prep, dg, staging, s, g->ev[1])) != hipSuccess) return r;
     if ((r = hipEventRecord(g->ev[2], s)) != hipSuccess) return r;
     return hipStreamSynchronize(s);
   };
   e = run();
-  hipFree(staging);
+  (void)hipFree(staging);
   if (e != hipSuccess) return cleanup_fail(EG_EDEVICE, "upload/layout/reverse CSR", e);
   if (st) {
     memset(st, 0, sizeof *st);
     float ms = 0;
-    hipEventElapsedTime(&ms, g->ev[0], g->ev[1]);
+    (void)hipEventElapsedTime(&ms, g->ev[0], g->ev[1]);
     st->t_upload = ms * 1e-3;
-    hipEventElapsedTime(&ms, g->ev[1], g->ev[2]);
+    (void)hipEventElapsedTime(&ms, g->ev[1], g->ev[2]);
     st->t_rcsr = ms * 1e-3;
   }
   *out = g;
@@ -386,7 +432,7 @@ int eg_create(eg_ctx* ctx, const eg_game_desc* desc, eg_game** out, eg_stats* st
 
 int eg_destroy(eg_game* g) {
   if (!g) return fail(EG_EINVAL, "null game");
-  hipSetDevice(g->ctx->cfg.device);
+  (void)hipSetDevice(g->ctx->cfg.device);
   game_free(g);
   return EG_OK;
 }
@@ -453,7 +499,7 @@ int eg_solve_ex(eg_game* g, const eg_solve_opts* opts, int64_t* credits, eg_stat
     HIPCHK(hipStreamSynchronize(s));
     {
       float ms = 0;
-      hipEventElapsedTime(&ms, g->ev[3], g->ev[4]);
+      (void)hipEventElapsedTime(&ms, g->ev[3], g->ev[4]);
       t_kernels += ms * 1e-3;
     }
     bool next_dense = dense;
@@ -499,9 +545,9 @@ int eg_solve_ex(eg_game* g, const eg_solve_opts* opts, int64_t* credits, eg_stat
     st->changes = g->h_stats[eg::S_CHANGES];
     st->scanned_preds = g->h_stats[eg::S_SCANNED];
     float ms = 0;
-    hipEventElapsedTime(&ms, g->ev[0], g->ev[1]);
+    (void)hipEventElapsedTime(&ms, g->ev[0], g->ev[1]);
     st->t_solve = ms * 1e-3;
-    hipEventElapsedTime(&ms, g->ev[1], g->ev[2]);
+    (void)hipEventElapsedTime(&ms, g->ev[1], g->ev[2]);
     st->t_d2h = ms * 1e-3;
     const double vb = g->vbits / 8;
     // algorithmic bytes: per relaxed edge the {target, weight} pair and f(target);
@@ -523,8 +569,11 @@ int eg_solve(eg_game* g, int64_t* credits, eg_stats* st) { return eg_solve_ex(g,
 
 int eg_submit(eg_ctx* ctx, const eg_game_desc* desc, eg_ticket* out) {
   if (!ctx || !desc || !out) return fail(EG_EINVAL, "null argument");
-  return eg::server_submit(ctx->server ? ctx->server : (ctx->server = eg::server_create(ctx->cfg, ctx->stream)),
-                           desc, out);
+  {
+    std::lock_guard<std::mutex> lock(ctx->server_mu);
+    if (!ctx->server) ctx->server = eg::server_create(ctx->cfg, ctx->stream);
+  }
+  return eg::server_submit(ctx->server, desc, out);
 }
 
 int eg_poll(eg_ctx* ctx, eg_ticket t, int64_t* credits, eg_stats* st) {
@@ -533,10 +582,39 @@ int eg_poll(eg_ctx* ctx, eg_ticket t, int64_t* credits, eg_stats* st) {
   return eg::server_poll(ctx->server, t, credits, st);
 }
 
+int eg_wait(eg_ctx* ctx, eg_ticket t, int64_t* credits, eg_stats* st, double timeout_s) {
+  if (!ctx) return fail(EG_EINVAL, "null context");
+  if (!ctx->server) return fail(EG_ENOTFOUND, "unknown ticket %llu", (unsigned long long)t);
+  return eg::server_wait(ctx->server, t, credits, st, timeout_s);
+}
+
+int eg_solve_batch(eg_ctx* ctx, const eg_game_desc* games, int count, int64_t* const* credits, eg_stats* stats) {
+  if (!ctx || (count > 0 && (!games || !credits))) return fail(EG_EINVAL, "null argument");
+  if (count < 0) return fail(EG_EINVAL, "count = %d", count);
+  std::vector<eg_ticket> t((size_t)count);
+  int rc = EG_OK;
+  int submitted = 0;
+  for (; submitted < count; submitted++) {
+    rc = eg_submit(ctx, &games[submitted], &t[(size_t)submitted]);
+    if (rc != EG_OK) break;
+  }
+  const std::string submit_err = rc != EG_OK ? t_err : std::string();
+  int first_err = rc;
+  for (int i = 0; i < submitted; i++) {
+    if (first_err != EG_OK) {
+      eg_cancel(ctx, t[(size_t)i]);
+      eg_wait(ctx, t[(size_t)i], nullptr, nullptr, 0);
+      continue;
+    }
+    const int r = eg_wait(ctx, t[(size_t)i], credits[i], stats ? &stats[i] : nullptr, 0);
+    if (r != EG_OK) first_err = r;
+  }
+  if (!submit_err.empty()) t_err = submit_err;
+  return first_err;
+}
+
 int eg_cancel(eg_ctx* ctx, eg_ticket t) {
   if (!ctx) return fail(EG_EINVAL, "null context");
   if (!ctx->server) return fail(EG_ENOTFOUND, "unknown ticket %llu", (unsigned long long)t);
   return eg::server_cancel(ctx->server, t);
 }
-
-}  // extern "C"

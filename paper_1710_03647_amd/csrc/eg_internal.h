@@ -4,6 +4,11 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
+#include <vector>
+
+#include "eg.h"
+
 namespace eg {
 
 // Row starts are uint32 (m < 2^31); bit 31 of rs[v] carries the owner of v
@@ -41,7 +46,51 @@ struct DevGame {
   unsigned long long* stats;  // S_WORDS totals
   int64_t bound;            // B
   int64_t top;              // device encoding of TOP: B + P + 1, P = largest stored weight
+  int32_t vbits;            // 32 or 64: width of f
 };
+
+// Slot states of the batched iteration.
+constexpr uint32_t SLOT_FREE = 0, SLOT_RUN = 1, SLOT_DONE = 2;
+
+// Slot table of the batched iteration (device pointers, passed by value).
+enum BatchCtl : int { B_EPOCH = 0, B_TASKS = 1, B_WORDS = 4 };
+struct BatchTable {
+  const DevGame* games;       // nslots descriptors
+  uint32_t* state;            // SLOT_FREE / SLOT_RUN / SLOT_DONE
+  uint32_t* join;             // epoch in which the game runs its round 1
+  uint32_t* rounds;           // rounds run, written when the game is retired
+  uint32_t* task_begin;       // nslots + 1: first task of each slot in the current epoch
+  unsigned long long* st;     // nslots * S_WORDS counters
+  uint32_t* ctl;              // B_WORDS
+  uint32_t nslots;
+};
+
+// Device layout of one game: every array in one allocation.
+enum LayoutPart : int {
+  L_RS, L_EDGES, L_ROFF, L_RSRC, L_F, L_ACT, L_WL0, L_WL1, L_OUT, L_CTRL, L_STATS, L_ACTBITS, L_BLK, L_SLOTS, L_N
+};
+struct GameLayout {
+  size_t off[L_N];
+  size_t total;
+};
+GameLayout plan_layout(int32_t n, int64_t m, int vbits, size_t nblocks);
+void bind_layout(DevGame& dg, char* base, const GameLayout& L, int32_t n, int64_t m, int vbits);
+
+// Host-side preparation of a validated game.
+struct HostPrep {
+  eg_game_info info;
+  int64_t clamp;                   // largest stored weight P
+  std::vector<uint32_t> act_bits;  // initially active vertices
+};
+int check_host(const eg_game_desc* d, int bound_mode, eg_game_info* info, std::string* why,
+               int64_t* clamp_out, std::vector<uint32_t>* act_bits);
+// H2D copy (host descriptor) or device-to-device use (device descriptor), layout,
+// initial-activity flags and predecessor lists into a bound DevGame, on stream s.
+// staging: scratch of staging_bytes(n, m, host) bytes, free once s has completed.
+size_t staging_bytes(int32_t n, int64_t m, bool host_inputs);
+hipError_t upload_game(const eg_game_desc* d, const HostPrep& prep, DevGame& dg, void* staging, hipStream_t s,
+                       hipEvent_t after_layout);
+hipError_t launch_epoch(const BatchTable& bt, int grid, hipStream_t s);
 
 // Layout and predecessor lists (eg_kernels.hip)
 hipError_t launch_layout(const int64_t* off, const uint8_t* owner_bits, const int32_t* tgt,

@@ -357,17 +357,138 @@ __global__ __launch_bounds__(BLOCK) void k_compact(DevGame g, uint32_t r) {
   }
 }
 
-// One round of Alg. 3 over L_r.  Every active vertex is lifted in place
-// (chaotic updates are exact, see above) and the predecessors of every vertex
-// whose value rose form L_{r+1}.  A block takes a tile of TILE list entries
-// (sparse) or vertices (dense) and flattens the work: the out-edges of the
-// tile's active vertices are numbered by a block scan of their degrees, each
-// thread takes UNROLL edges at a stride of BLOCK (coalesced {target, weight}
-// reads, UNROLL gathers of f in flight) and folds its terms into the vertex's
-// LDS key with an atomic min (player 1 keys are negated terms, so one min
-// serves both players, Def. 6).  The predecessor lists of the changed
-// vertices are flattened the same way.  Any degree distribution is balanced
-// across the block.
+// Per-thread counters of a round (summed per block at the end).
+struct Counters {
+  unsigned long long lifts = 0, edges = 0, changes = 0, pushes = 0, scanned = 0;
+};
+
+// One tile of a round of Alg. 3 (block-uniform call).  The tile holds TILE
+// entries of the active set: list entries (sparse) or vertex ids (dense).
+// Every active vertex is lifted in place (chaotic updates are exact, see
+// above) and the predecessors of every vertex whose value rose join L_{r+1}.
+// The block flattens the work: the out-edges of the tile's active vertices
+// are numbered by a block scan of their degrees, each thread takes UNROLL
+// edges at a stride of BLOCK (coalesced {target, weight} reads, UNROLL
+// gathers of f in flight) and folds its terms into the vertex's LDS key with
+// an atomic min (player-1 keys are negated terms, so one min serves both
+// players, Def. 6).  The predecessor lists of the changed vertices are
+// flattened the same way.  Any degree distribution is balanced across the
+// block.  Returns with the shared arrays still in use: the caller
+// synchronises before the next tile.
+template <typename V, bool DENSE>
+__device__ __forceinline__ void round_tile(const DevGame& g, RoundShared<V>& sh, uint32_t r, uint32_t t,
+                                           uint32_t items, Counters& c) {
+  const uint32_t tid = threadIdx.x;
+  V* f = (V*)g.f;
+  const V bound = (V)g.bound, top = (V)g.top;
+  uint8_t* act_cur = (r & 1) ? g.act1 : g.act0;
+  uint8_t* act_next = (r & 1) ? g.act0 : g.act1;
+  const int32_t* wl_in = (r & 1) ? g.wl1 : g.wl0;
+  int32_t* wl_out = (r & 1) ? g.wl0 : g.wl1;
+  uint32_t* cnt_out = &g.ctrl[C_CNT0 + (r + 1) % 3];
+
+  const uint32_t idx = t * TILE + tid;
+  int32_t v = -1;
+  if (idx < items) {
+    if (DENSE) v = act_cur[idx] ? (int32_t)idx : -1;
+    else v = wl_in[idx];
+  }
+  uint32_t raw = 0, deg = 0, pb = 0, pe = 0;
+  V old = 0;
+  if (v >= 0) {
+    act_cur[v] = 0;  // consumed
+    raw = load_stream(g.rs + v);
+    deg = (load_stream(g.rs + v + 1) & ROW_MASK) - (raw & ROW_MASK);
+    old = f[v];
+    pb = load_stream(g.rev_off + v);
+    pe = load_stream(g.rev_off + v + 1);
+  }
+  uint32_t E;
+  const uint32_t ex = block_excl_scan(deg, sh.wsum, &E);
+  sh.epre[tid] = ex;
+  if (tid == BLOCK - 1) sh.epre[BLOCK] = E;
+  sh.ebeg[tid] = raw;
+  sh.key[tid] = (raw & OWNER_BIT) ? V(0) : std::numeric_limits<V>::max();
+  __syncthreads();
+  if (E == 0) return;  // block-uniform: no active vertex in this tile
+
+  for (uint32_t x0 = 0; x0 < E; x0 += BLOCK * UNROLL) {
+    uint32_t slot[UNROLL];
+    int2 ed[UNROLL];
+    V fu[UNROLL];
+#pragma unroll
+    for (int j = 0; j < UNROLL; j++) {
+      const uint32_t x = x0 + j * BLOCK + tid;
+      slot[j] = BLOCK;
+      if (x < E) {
+        const uint32_t s = find_range(sh.epre, x);
+        slot[j] = s;
+        ed[j] = load_edge(g.edges, (sh.ebeg[s] & ROW_MASK) + (x - sh.epre[s]));
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < UNROLL; j++)
+      if (slot[j] < BLOCK) fu[j] = f[ed[j].x];
+#pragma unroll
+    for (int j = 0; j < UNROLL; j++)
+      if (slot[j] < BLOCK) {
+        V tm = fu[j] - (V)ed[j].y;
+        tm = tm > V(0) ? tm : V(0);
+        __hip_atomic_fetch_min(&sh.key[slot[j]], (sh.ebeg[slot[j]] & OWNER_BIT) ? -tm : tm,
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+  }
+  __syncthreads();
+
+  uint32_t ideg = 0;
+  if (v >= 0) {
+    const V k = sh.key[tid];
+    V nv = (raw & OWNER_BIT) ? -k : k;
+    if (nv > bound) nv = top;
+    c.lifts++;
+    c.edges += deg;
+    if (nv != old) {
+      f[v] = nv;
+      c.changes++;
+      ideg = pe - pb;
+    }
+  }
+  uint32_t P;
+  const uint32_t pex = block_excl_scan(ideg, sh.wsum, &P);
+  sh.ppre[tid] = pex;
+  if (tid == BLOCK - 1) sh.ppre[BLOCK] = P;
+  sh.pbeg[tid] = pb;
+  c.scanned += ideg;
+  __syncthreads();
+  for (uint32_t x0 = 0; x0 < P; x0 += BLOCK * UNROLL) {
+    int32_t pr[UNROLL];
+#pragma unroll
+    for (int j = 0; j < UNROLL; j++) {
+      const uint32_t x = x0 + j * BLOCK + tid;
+      pr[j] = -1;
+      if (x < P) {
+        const uint32_t s = find_range(sh.ppre, x);
+        pr[j] = load_stream(g.rev_src + sh.pbeg[s] + (x - sh.ppre[s]));
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < UNROLL; j++) activate<DENSE>(g, sh, pr[j] >= 0, pr[j], act_next, wl_out, cnt_out, c.pushes);
+  }
+}
+
+// Sum the counters of the block into LDS (sh.st must be zero on entry).
+template <typename V>
+__device__ __forceinline__ void block_counters(RoundShared<V>& sh, const Counters& c) {
+  atomicAdd(&sh.st[S_LIFTS], c.lifts);
+  atomicAdd(&sh.st[S_EDGES], c.edges);
+  atomicAdd(&sh.st[S_CHANGES], c.changes);
+  atomicAdd(&sh.st[S_PUSHES], c.pushes);
+  atomicAdd(&sh.st[S_SCANNED], c.scanned);
+  __syncthreads();
+}
+
+// One round of Alg. 3 over L_r of one game: blocks take the tiles of the
+// active set in turn (see round_tile).
 template <typename V, bool DENSE>
 __global__ __launch_bounds__(BLOCK) void k_round(DevGame g, uint32_t r) {
   __shared__ RoundShared<V> sh;
@@ -386,113 +507,16 @@ __global__ __launch_bounds__(BLOCK) void k_round(DevGame g, uint32_t r) {
   }
   if (tid == 0) sh.n_push = 0;
   if (tid < S_WORDS) sh.st[tid] = 0;
-  V* f = (V*)g.f;
-  const V bound = (V)g.bound, top = (V)g.top;
-  uint8_t* act_cur = (r & 1) ? g.act1 : g.act0;
-  uint8_t* act_next = (r & 1) ? g.act0 : g.act1;
-  const int32_t* wl_in = (r & 1) ? g.wl1 : g.wl0;
-  int32_t* wl_out = (r & 1) ? g.wl0 : g.wl1;
-  uint32_t* cnt_out = &g.ctrl[C_CNT0 + (r + 1) % 3];
-  unsigned long long lifts = 0, edges_read = 0, changes = 0, pushes = 0, scanned = 0;
+  Counters c;
   const uint32_t ntiles = (items + TILE - 1) / TILE;
-
   for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     __syncthreads();  // the previous tile is done with the shared arrays
-    const uint32_t idx = t * TILE + tid;
-    int32_t v = -1;
-    if (idx < items) {
-      if (DENSE) v = act_cur[idx] ? (int32_t)idx : -1;
-      else v = wl_in[idx];
-    }
-    uint32_t raw = 0, deg = 0, pb = 0, pe = 0;
-    V old = 0;
-    if (v >= 0) {
-      act_cur[v] = 0;  // consumed
-      raw = load_stream(g.rs + v);
-      deg = (load_stream(g.rs + v + 1) & ROW_MASK) - (raw & ROW_MASK);
-      old = f[v];
-      pb = load_stream(g.rev_off + v);
-      pe = load_stream(g.rev_off + v + 1);
-    }
-    uint32_t E;
-    const uint32_t ex = block_excl_scan(deg, sh.wsum, &E);
-    sh.epre[tid] = ex;
-    if (tid == BLOCK - 1) sh.epre[BLOCK] = E;
-    sh.ebeg[tid] = raw;
-    sh.key[tid] = (raw & OWNER_BIT) ? V(0) : std::numeric_limits<V>::max();
-    __syncthreads();
-    if (E == 0) continue;  // block-uniform: no active vertex in this tile
-
-    for (uint32_t x0 = 0; x0 < E; x0 += BLOCK * UNROLL) {
-      uint32_t slot[UNROLL];
-      int2 ed[UNROLL];
-      V fu[UNROLL];
-#pragma unroll
-      for (int j = 0; j < UNROLL; j++) {
-        const uint32_t x = x0 + j * BLOCK + tid;
-        slot[j] = BLOCK;
-        if (x < E) {
-          const uint32_t s = find_range(sh.epre, x);
-          slot[j] = s;
-          ed[j] = load_edge(g.edges, (sh.ebeg[s] & ROW_MASK) + (x - sh.epre[s]));
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < UNROLL; j++)
-        if (slot[j] < BLOCK) fu[j] = f[ed[j].x];
-#pragma unroll
-      for (int j = 0; j < UNROLL; j++)
-        if (slot[j] < BLOCK) {
-          V tm = fu[j] - (V)ed[j].y;
-          tm = tm > V(0) ? tm : V(0);
-          __hip_atomic_fetch_min(&sh.key[slot[j]], (sh.ebeg[slot[j]] & OWNER_BIT) ? -tm : tm,
-                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        }
-    }
-    __syncthreads();
-
-    uint32_t ideg = 0;
-    if (v >= 0) {
-      const V k = sh.key[tid];
-      V nv = (raw & OWNER_BIT) ? -k : k;
-      if (nv > bound) nv = top;
-      lifts++;
-      edges_read += deg;
-      if (nv != old) {
-        f[v] = nv;
-        changes++;
-        ideg = pe - pb;
-      }
-    }
-    uint32_t P;
-    const uint32_t pex = block_excl_scan(ideg, sh.wsum, &P);
-    sh.ppre[tid] = pex;
-    if (tid == BLOCK - 1) sh.ppre[BLOCK] = P;
-    sh.pbeg[tid] = pb;
-    scanned += ideg;
-    __syncthreads();
-    for (uint32_t x0 = 0; x0 < P; x0 += BLOCK * UNROLL) {
-      int32_t pr[UNROLL];
-#pragma unroll
-      for (int j = 0; j < UNROLL; j++) {
-        const uint32_t x = x0 + j * BLOCK + tid;
-        pr[j] = -1;
-        if (x < P) {
-          const uint32_t s = find_range(sh.ppre, x);
-          pr[j] = load_stream(g.rev_src + sh.pbeg[s] + (x - sh.ppre[s]));
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < UNROLL; j++) activate<DENSE>(g, sh, pr[j] >= 0, pr[j], act_next, wl_out, cnt_out, pushes);
-    }
+    round_tile<V, DENSE>(g, sh, r, t, items, c);
   }
-  atomicAdd(&sh.st[S_LIFTS], lifts);
-  atomicAdd(&sh.st[S_EDGES], edges_read);
-  atomicAdd(&sh.st[S_CHANGES], changes);
-  atomicAdd(&sh.st[S_PUSHES], pushes);
-  atomicAdd(&sh.st[S_SCANNED], scanned);
-  __syncthreads();
+  block_counters(sh, c);
   if (!DENSE) {
+    uint32_t* cnt_out = &g.ctrl[C_CNT0 + (r + 1) % 3];
+    int32_t* wl_out = (r & 1) ? g.wl0 : g.wl1;
     const uint32_t nf = sh.n_push < (uint32_t)PUSH_CAP ? sh.n_push : (uint32_t)PUSH_CAP;
     if (tid == 0) sh.base = nf ? atomicAdd(cnt_out, nf) : 0u;
     __syncthreads();
@@ -503,6 +527,109 @@ __global__ __launch_bounds__(BLOCK) void k_round(DevGame g, uint32_t r) {
     g.blk_chg[blockIdx.x] = (uint32_t)sh.st[S_CHANGES];
     if (sh.st[S_CHANGES]) g.ctrl[C_ANY0 + r % 3] = 1;
   }
+}
+
+// ---------------------------------------------------------------- batched games
+//
+// Many games share one launch per round.  The slot table holds one DevGame
+// per resident game; game s runs its round r = epoch - join[s] + 1 in epoch
+// `epoch`, independently of the others.  Each epoch is two launches: k_plan
+// (one block) retires the games whose previous round raised nothing and lays
+// out the tasks of the epoch, one per tile of every running game (dense
+// representation); k_batch_round (a fixed grid) takes tasks in turn.
+
+__global__ __launch_bounds__(1024) void k_plan(BatchTable bt) {
+  __shared__ uint32_t wsum[1024 / WAVE];
+  __shared__ uint32_t carry;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t epoch = bt.ctl[B_EPOCH] + 1;
+  if (tid == 0) carry = 0;
+  __syncthreads();
+  for (uint32_t base = 0; base < bt.nslots; base += 1024) {
+    const uint32_t s = base + tid;
+    uint32_t tasks = 0;
+    if (s < bt.nslots && bt.state[s] == SLOT_RUN) {
+      const uint32_t r = epoch - bt.join[s] + 1;
+      const DevGame& g = bt.games[s];
+      if (g.ctrl[C_ANY0 + (r - 1) % 3] == 0) {  // round r-1 raised nothing: L_r is empty
+        bt.state[s] = SLOT_DONE;
+        bt.rounds[s] = r - 1;
+      } else {
+        g.ctrl[C_ANY0 + (r + 1) % 3] = 0;  // written by round r+1
+        tasks = ((uint32_t)g.n + TILE - 1) / TILE;
+      }
+    }
+    // exclusive scan of tasks over the 1024 slots of this chunk
+    const uint32_t lane = lane_id(), wid = tid / WAVE;
+    uint32_t incl = tasks;
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+      const uint32_t y = __shfl_up(incl, o, WAVE);
+      if (lane >= (uint32_t)o) incl += y;
+    }
+    if (lane == WAVE - 1) wsum[wid] = incl;
+    __syncthreads();
+    uint32_t off = carry, tot = 0;
+    for (int w = 0; w < 1024 / WAVE; w++) {
+      off += (uint32_t)w < wid ? wsum[w] : 0u;
+      tot += wsum[w];
+    }
+    if (s < bt.nslots) bt.task_begin[s] = off + incl - tasks;
+    __syncthreads();
+    if (tid == 0) carry += tot;
+    __syncthreads();
+  }
+  if (tid == 0) {
+    bt.task_begin[bt.nslots] = carry;
+    bt.ctl[B_TASKS] = carry;
+    bt.ctl[B_EPOCH] = epoch;
+  }
+}
+
+// slot whose task range holds task x (task_begin[0] = 0 <= x < task_begin[nslots])
+__device__ __forceinline__ uint32_t find_slot(const uint32_t* begin, uint32_t nslots, uint32_t x) {
+  uint32_t lo = 0, hi = nslots;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (begin[mid] <= x) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+template <typename V>
+__device__ __forceinline__ void batch_task(const BatchTable& bt, RoundShared<V>& sh, uint32_t s, uint32_t t,
+                                           uint32_t epoch) {
+  const DevGame& g = bt.games[s];
+  const uint32_t r = epoch - bt.join[s] + 1;
+  if (threadIdx.x < S_WORDS) sh.st[threadIdx.x] = 0;
+  Counters c;
+  round_tile<V, true>(g, sh, r, t, (uint32_t)g.n, c);
+  __syncthreads();
+  block_counters(sh, c);
+  if (threadIdx.x < S_WORDS && sh.st[threadIdx.x]) atomicAdd(&bt.st[s * S_WORDS + threadIdx.x], sh.st[threadIdx.x]);
+  if (threadIdx.x == 0 && sh.st[S_CHANGES]) g.ctrl[C_ANY0 + r % 3] = 1;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_batch_round(BatchTable bt) {
+  __shared__ RoundShared<int64_t> sh;
+  const uint32_t ntasks = bt.ctl[B_TASKS];
+  const uint32_t epoch = bt.ctl[B_EPOCH];
+  for (uint32_t x = blockIdx.x; x < ntasks; x += gridDim.x) {
+    __syncthreads();
+    const uint32_t s = find_slot(bt.task_begin, bt.nslots, x);
+    const uint32_t t = x - bt.task_begin[s];
+    if (bt.games[s].top <= INT32_MAX)  // 32-bit values (see the value width rule)
+      batch_task<int32_t>(bt, reinterpret_cast<RoundShared<int32_t>&>(sh), s, t, epoch);
+    else
+      batch_task<int64_t>(bt, sh, s, t, epoch);
+  }
+}
+
+hipError_t launch_epoch(const BatchTable& bt, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, s, bt);
+  hipLaunchKernelGGL(k_batch_round, dim3(grid), dim3(BLOCK), 0, s, bt);
+  return hipGetLastError();
 }
 
 // stats[k] = sum over blocks of slots[b][k]

@@ -13,6 +13,7 @@ void server_destroy(Server* s);
 int server_submit(Server* s, const eg_game_desc* desc, eg_ticket* out);
 int server_poll(Server* s, eg_ticket t, int64_t* credits, eg_stats* st);
 int server_cancel(Server* s, eg_ticket t);
+int server_wait(Server* s, eg_ticket t, int64_t* credits, eg_stats* st, double timeout_s);
 
 void set_error(const char* msg);
 const char* get_error();

@@ -27,7 +27,8 @@ ERROR_NAMES = {EG_EINVAL: "EG_EINVAL", EG_ENOMEM: "EG_ENOMEM", EG_EDEVICE: "EG_E
                EG_ECANCELED: "EG_ECANCELED", EG_PENDING: "EG_PENDING"}
 
 EXPORTS = ["eg_ctx_create", "eg_ctx_destroy", "eg_check", "eg_create", "eg_destroy", "eg_solve",
-           "eg_solve_ex", "eg_set_measure", "eg_submit", "eg_poll", "eg_cancel", "eg_last_error"]
+           "eg_solve_ex", "eg_set_measure", "eg_submit", "eg_poll", "eg_cancel", "eg_wait", "eg_solve_batch",
+           "eg_last_error"]
 
 
 class EgError(RuntimeError):
@@ -56,7 +57,8 @@ class eg_stats(ctypes.Structure):
                 ("t_upload", ctypes.c_double),
                 ("t_rcsr", ctypes.c_double), ("t_solve", ctypes.c_double), ("t_d2h", ctypes.c_double),
                 ("model_bytes", ctypes.c_double), ("achieved_gbps", ctypes.c_double),
-                ("t_round_kernels", ctypes.c_double), ("launched_rounds", ctypes.c_uint64),
+                ("t_round_kernels", ctypes.c_double), ("t_queue", ctypes.c_double),
+                ("t_latency", ctypes.c_double), ("launched_rounds", ctypes.c_uint64),
                 ("dense_rounds", ctypes.c_uint64)]
 
     def to_dict(self) -> dict:
@@ -107,6 +109,8 @@ def lib():
         L.eg_submit.argtypes = [vp, P(eg_game_desc), P(ctypes.c_uint64)]
         L.eg_poll.argtypes = [vp, ctypes.c_uint64, vp, P(eg_stats)]
         L.eg_cancel.argtypes = [vp, ctypes.c_uint64]
+        L.eg_wait.argtypes = [vp, ctypes.c_uint64, vp, P(eg_stats), ctypes.c_double]
+        L.eg_solve_batch.argtypes = [vp, P(eg_game_desc), ctypes.c_int, P(ctypes.c_void_p), P(eg_stats)]
         L.eg_last_error.argtypes = [vp]
         L.eg_last_error.restype = ctypes.c_char_p
         for name in EXPORTS[:-1]:
@@ -232,6 +236,29 @@ class Context:
 
     def cancel(self, ticket: int) -> int:
         return lib().eg_cancel(self.handle, ticket)
+
+    def wait(self, ticket: int, n: int, timeout_s: float = 0.0):
+        """Block until the ticket is done: (status, credits or None, stats dict or None)."""
+        out = np.empty(n, dtype=np.int64)
+        st = eg_stats()
+        rc = lib().eg_wait(self.handle, ticket, _ptr(out), ctypes.byref(st), timeout_s)
+        if rc == EG_OK:
+            return rc, out, st.to_dict()
+        if rc == EG_PENDING:
+            return rc, None, None
+        raise _err(rc, self.handle)
+
+    def solve_batch(self, games):
+        """Solve many games in the batched iteration: list of (credits, stats)."""
+        keep = [make_desc(g) for g in games]
+        descs = (eg_game_desc * len(games))(*[d for d, _ in keep])
+        outs = [np.empty(g.n, dtype=np.int64) for g in games]
+        ptrs = (ctypes.c_void_p * len(games))(*[o.ctypes.data for o in outs])
+        stats = (eg_stats * len(games))()
+        rc = lib().eg_solve_batch(self.handle, descs, len(games), ptrs, stats)
+        if rc != EG_OK:
+            raise _err(rc, self.handle)
+        return [(outs[i], stats[i].to_dict()) for i in range(len(games))]
 
 
 class Game:
