@@ -481,46 +481,64 @@ int eg_solve_ex(eg_game* g, const eg_solve_opts* opts, int64_t* credits, eg_stat
   uint32_t r = 1;
   uint64_t launched = 0;
   int status = EG_OK;
-  bool dense = active >= dense_at;
-  if (active && !dense) HIPCHK(eg::launch_compact(dg, 1, grid, s));
+  // representation of the active set: a flag sweep for large sets, a list
+  // for medium ones, and for small ones a single block running many rounds
+  enum { SPARSE, DENSE, SMALL };
+  auto pick = [&](uint64_t size) { return size <= eg::SMALL_LIMIT ? SMALL : size >= dense_at ? DENSE : SPARSE; };
+  int mode = pick(active);
+  if (active && mode != DENSE) HIPCHK(eg::launch_compact(dg, 1, grid, s));
   uint32_t batch = 2;
   double t_kernels = 0;  // device time of the round kernels (back to back within a batch)
   uint64_t dense_rounds = 0;
   while (active) {
-    uint32_t k = batch;
-    if (max_rounds && launched + k > max_rounds) k = (uint32_t)(max_rounds - launched);
+    uint64_t allowed = 64;
+    if (mode == SMALL) allowed = 8192;
+    else allowed = batch;
+    if (max_rounds) allowed = std::min<uint64_t>(allowed, max_rounds - launched);
     HIPCHK(hipEventRecord(g->ev[3], s));
-    for (uint32_t j = 0; j < k; j++) HIPCHK(eg::launch_round(dg, g->vbits, g->h, dense, r++, grid, s));
+    if (mode == SMALL) {
+      HIPCHK(eg::launch_rounds_small(dg, g->vbits, r, (uint32_t)allowed, eg::SMALL_LIMIT, s));
+    } else {
+      for (uint32_t j = 0; j < allowed; j++) HIPCHK(eg::launch_round(dg, g->vbits, g->h, mode == DENSE, r++, grid, s));
+    }
     HIPCHK(hipEventRecord(g->ev[4], s));
-    launched += k;
-    dense_rounds += dense ? k : 0;
     HIPCHK(hipMemcpyAsync(g->h_ctrl, dg.ctrl, 4 * eg::C_WORDS, hipMemcpyDeviceToHost, s));
-    if (dense) HIPCHK(hipMemcpyAsync(g->h_blk, dg.blk_chg, 4 * (size_t)grid, hipMemcpyDeviceToHost, s));
+    if (mode == DENSE) HIPCHK(hipMemcpyAsync(g->h_blk, dg.blk_chg, 4 * (size_t)grid, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     {
       float ms = 0;
       (void)hipEventElapsedTime(&ms, g->ev[3], g->ev[4]);
       t_kernels += ms * 1e-3;
     }
-    bool next_dense = dense;
-    if (dense) {
+    if (mode == SMALL) {
+      const uint32_t next_r = g->h_ctrl[eg::C_NEXT];
+      launched += next_r - r;
+      r = next_r;
+    } else {
+      launched += allowed;
+      dense_rounds += mode == DENSE ? allowed : 0;
+    }
+    int next_mode = mode;
+    if (mode == DENSE) {
       if (g->h_ctrl[eg::C_ANY0 + (r - 1) % 3] == 0) break;  // nothing rose in the last round
       uint64_t changed = 0;
       for (int b = 0; b < grid; b++) changed += g->h_blk[b];
       // predecessors of the changed vertices, at most
-      if ((double)changed * g->avg_indeg < (double)dense_at / 4) next_dense = false;
+      const double est = (double)changed * g->avg_indeg;
+      if (est <= eg::SMALL_LIMIT) next_mode = SMALL;
+      else if (est < (double)dense_at / 4) next_mode = SPARSE;
     } else {
       const uint64_t next = g->h_ctrl[eg::C_CNT0 + r % 3];
       if (next == 0) break;
-      if (next >= dense_at) next_dense = true;
+      next_mode = pick(next);
     }
     if ((max_rounds && launched >= max_rounds) || (budget > 0 && now_s() - t0 > budget) || r > 0xFFFFFF00u) {
       status = EG_ETIMEDOUT;
       break;
     }
-    if (next_dense != dense) {
-      if (!next_dense) HIPCHK(eg::launch_compact(dg, r, grid, s));
-      dense = next_dense;
+    if (next_mode != mode) {
+      if (mode == DENSE) HIPCHK(eg::launch_compact(dg, r, grid, s));
+      mode = next_mode;
       batch = 2;
     } else if (batch < 64) {
       batch *= 2;

@@ -21,6 +21,7 @@ enum Ctrl : int {
   C_CNT0 = 0,    // C_CNT0 + (r % 3): length of the active list of round r (sparse rounds)
   C_ANY0 = 3,    // C_ANY0 + (r % 3): nonzero if some value rose in round r (round 0 = init)
   C_ROUNDS = 6,  // rounds with a non-empty active set
+  C_NEXT = 7,    // single-block driver: the round to run next
   C_WORDS = 8
 };
 // counters per block (slots) and totals (stats), uint64
@@ -107,6 +108,9 @@ hipError_t launch_init(const DevGame& g, int vbits, int resume, int grid, hipStr
 hipError_t launch_compact(const DevGame& g, uint32_t r, int grid, hipStream_t s);
 hipError_t launch_round(const DevGame& g, int vbits, int h, bool dense, uint32_t r, int grid, hipStream_t s);
 hipError_t launch_reduce_stats(const DevGame& g, int nblocks, hipStream_t s);
+hipError_t launch_rounds_small(const DevGame& g, int vbits, uint32_t r0, uint32_t max_rounds, uint32_t limit,
+                               hipStream_t s);
+constexpr uint32_t SMALL_LIMIT = 1024;  // active-set size up to which one block runs the rounds
 hipError_t launch_output(const DevGame& g, int vbits, int64_t* out, hipStream_t s);
 hipError_t launch_input(const DevGame& g, int vbits, const int64_t* in, hipStream_t s);
 

@@ -529,6 +529,69 @@ __global__ __launch_bounds__(BLOCK) void k_round(DevGame g, uint32_t r) {
   }
 }
 
+// Many rounds of one game in a single block, for small active sets: a round
+// of a few tiles costs a few dependent cache hits here instead of a kernel
+// launch.  Starts at round r0 (sparse list), stops before a round whose list
+// is empty (the fixpoint) or longer than `limit`, or after `max_rounds`;
+// ctrl[C_NEXT] receives the round to run next.  All waves of the block share
+// one CU and its caches, so the block barrier orders rounds.
+template <typename V>
+__global__ __launch_bounds__(BLOCK) void k_rounds_small(DevGame g, uint32_t r0, uint32_t max_rounds,
+                                                         uint32_t limit) {
+  __shared__ RoundShared<V> sh;
+  __shared__ uint32_t s_items;
+  __shared__ int s_changed;
+  const uint32_t tid = threadIdx.x;
+  if (tid < S_WORDS) sh.st[tid] = 0;
+  Counters c;
+  uint32_t r = r0;
+  for (uint32_t k = 0; k < max_rounds; k++, r++) {
+    __syncthreads();
+    if (tid == 0) {
+      const uint32_t items = g.ctrl[C_CNT0 + r % 3];
+      s_items = items;
+      s_changed = 0;
+      sh.n_push = 0;
+      if (items != 0 && items <= limit) {
+        g.ctrl[C_CNT0 + (r + 2) % 3] = 0;
+        g.ctrl[C_ANY0 + (r + 1) % 3] = 0;
+        g.ctrl[C_ROUNDS] += 1;
+      }
+    }
+    __syncthreads();
+    const uint32_t items = s_items;
+    if (items == 0 || items > limit) break;
+    const unsigned long long before = c.changes;
+    const uint32_t ntiles = (items + TILE - 1) / TILE;
+    for (uint32_t t = 0; t < ntiles; t++) {
+      __syncthreads();
+      round_tile<V, false>(g, sh, r, t, items, c);
+    }
+    __syncthreads();
+    if (c.changes != before) s_changed = 1;
+    uint32_t* cnt_out = &g.ctrl[C_CNT0 + (r + 1) % 3];
+    int32_t* wl_out = (r & 1) ? g.wl0 : g.wl1;
+    const uint32_t nf = sh.n_push < (uint32_t)PUSH_CAP ? sh.n_push : (uint32_t)PUSH_CAP;
+    if (tid == 0) sh.base = nf ? atomicAdd(cnt_out, nf) : 0u;
+    __syncthreads();
+    for (uint32_t i = tid; i < nf; i += BLOCK) wl_out[sh.base + i] = sh.push[i];
+    if (tid == 0 && s_changed) g.ctrl[C_ANY0 + r % 3] = 1;
+  }
+  __syncthreads();
+  block_counters(sh, c);
+  if (tid < S_WORDS) g.slots[tid] += sh.st[tid];
+  if (tid == 0) g.ctrl[C_NEXT] = r;
+}
+
+hipError_t launch_rounds_small(const DevGame& g, int vbits, uint32_t r0, uint32_t max_rounds, uint32_t limit,
+                               hipStream_t s) {
+  if (vbits == 32)
+    hipLaunchKernelGGL(k_rounds_small<int32_t>, dim3(1), dim3(BLOCK), 0, s, g, r0, max_rounds, limit);
+  else
+    hipLaunchKernelGGL(k_rounds_small<int64_t>, dim3(1), dim3(BLOCK), 0, s, g, r0, max_rounds, limit);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- batched games
 //
 // Many games share one launch per round.  The slot table holds one DevGame
