@@ -14,13 +14,18 @@ Also reported:
                 against the 8 TB/s HBM peak; `traffic` from committed rocprofv3
                 counter summaries when they match the current kernel source;
   cpu_baseline  the CPU oracle (sequential FIFO worklist, one core) on a
-                bounded sample of the same game: its first lifts, ~15 s of work.
+                bounded sample of the same game: its first lifts, ~15 s of work;
+  serving       the first --serve-games games of the serving stream (n
+                log-uniform in [1e3, 1e5], out-degree U{2..16}, W log-uniform in
+                [10, 1000]): one-game-at-a-time solves, the batched server's
+                closed-loop capacity, and Poisson arrivals at 0.8x that capacity
+                with p50/p99 latency (arrival to result).
 
 Flags: --gpus N (only 1 is supported: the solver runs on one GPU),
 --steps K, --warmup W, --config {uniform,plain,rmat,torus}, --no-cpu-baseline,
 --sweep R (instead of solves: R full-frontier lift rounds, every vertex active),
 --max-rounds M (profiling only: stops each solve after M rounds; the line is
-then marked partial).
+then marked partial), --serve-games G (0 = no serving report).
 """
 from __future__ import annotations
 
@@ -101,6 +106,50 @@ def cpu_baseline(game, seconds):
                       f"{dt:.1f} s, one thread)"}
 
 
+def serving_report(eg, synth, count):
+    """One-at-a-time vs batched serving on the first `count` stream games."""
+    import numpy as np
+
+    games = [synth.gen_stream_game(i) for i in range(count)]
+    with eg.Context(0) as ctx:
+        t0 = time.perf_counter()
+        for g in games:
+            with ctx.create(g) as h:
+                h.solve()
+        t_one = time.perf_counter() - t0
+    log(f"[bench] serving: one at a time {count / t_one:.2f} games/s ({t_one:.1f} s)")
+    res = {"games": count, "workload": f"first {count} games of the serving stream (seed 5)",
+           "one_at_a_time_games_per_s": count / t_one}
+    with eg.Context(0, hbm_budget_bytes=16 << 30) as ctx:
+        t0 = time.perf_counter()
+        tickets = [ctx.submit(g) for g in games]
+        for g, t in zip(games, tickets):
+            ctx.wait(t, g.n)
+        t_cap = time.perf_counter() - t0
+        cap = count / t_cap
+        log(f"[bench] serving: batched closed loop {cap:.2f} games/s ({t_cap:.1f} s)")
+        rate = 0.8 * cap
+        arrivals = synth.poisson_arrivals(count, rate)
+        t0 = time.perf_counter()
+        tickets = []
+        for g, a in zip(games, arrivals):
+            d = a - (time.perf_counter() - t0)
+            if d > 0:
+                time.sleep(d)
+            tickets.append(ctx.submit(g))
+        lat = []
+        for g, t in zip(games, tickets):
+            rc, f, st = ctx.wait(t, g.n)
+            lat.append(st["t_latency"])
+        t_poi = time.perf_counter() - t0
+    res.update({"batched_capacity_games_per_s": cap, "poisson_rate_per_s": rate,
+                "poisson_games_per_s": count / t_poi,
+                "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
+                "batched_vs_one_at_a_time": cap / (count / t_one)})
+    log(f"[bench] serving: Poisson {rate:.2f}/s -> p50 {res['p50_latency_s']:.3f} s, p99 {res['p99_latency_s']:.3f} s")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -111,6 +160,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--sweep", type=int, default=0)
     ap.add_argument("--max-rounds", type=int, default=0)
+    ap.add_argument("--serve-games", type=int, default=32)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported; the solver runs on one GPU "
@@ -194,10 +244,12 @@ def main():
     }
     if partial:
         line["partial"] = f"solves stopped after {args.max_rounds} rounds (profiling run)"
-    if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(game, args.cpu_seconds)
     g.destroy()
     ctx.close()
+    if args.serve_games and not args.sweep and not partial:
+        line["serving"] = serving_report(eg, synth, args.serve_games)
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(game, args.cpu_seconds)
     print(json.dumps(line), flush=True)
 
 

@@ -44,7 +44,6 @@ double now_s() {
 
 namespace eg {
 
-GameLayout plan_layout(int32_t n, int64_t m, int vbits, size_t nblk);
 void set_error(const char* msg) { t_err = msg; }
 const char* get_error() { return t_err.c_str(); }
 
@@ -118,7 +117,7 @@ int check_host(const eg_game_desc* d, int bound_mode, eg_game_info* info, std::s
     info->value_bits = hi < ((__int128)1 << 31) ? 32 : 64;
     info->max_outdeg = max_out;
     info->max_indeg = max_in;
-    info->device_bytes = plan_layout(n, d->m, info->value_bits, 1).total;
+    info->device_bytes = plan_layout(n, d->m, info->value_bits, 1, choose_parts(n, d->m, info->value_bits, 0)).total;
   }
   return EG_OK;
 }
@@ -149,6 +148,7 @@ struct eg_game {
   int64_t* out64 = nullptr;
   size_t arena_bytes = 0;
   int grid = 1;
+  int part_grid = 8;
   double avg_indeg = 1;
   uint32_t* h_blk = nullptr;
   uint32_t* h_ctrl = nullptr;
@@ -196,7 +196,13 @@ int eg_ctx_create(const eg_config* cfg, eg_ctx** out) {
     }
     ctx->own_stream = true;
   }
-  ctx->grid = eg::round_grid(c.device);
+  if (c.blocks_per_cu < 0 || c.blocks_per_cu > 32 || c.dense_div < 0 || c.small_limit < 0 || c.small_limit > 65536 ||
+      c.partition < 0 || c.partition > 2) {
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+    return fail(EG_EINVAL, "launch-shape field out of range");
+  }
+  ctx->grid = eg::round_grid(c.device) / 8 * (c.blocks_per_cu ? c.blocks_per_cu : 8);
   *out = ctx;
   return EG_OK;
 }
@@ -260,11 +266,24 @@ static int host_view(const eg_game_desc* desc, hipStream_t s, HostCopy& hc, eg_g
 
 namespace eg {
 
-GameLayout plan_layout(int32_t n, int64_t m, int vbits, size_t nblk) {
+// Dense rounds of games whose f does not fit one XCD's L2 with room to spare
+// use 8 target slices (one per XCD); the tile-local source index needs
+// targets below 2^22.
+uint32_t choose_parts(int32_t n, int64_t m, int vbits, int mode) {
+  if (mode == 1 || n > (1 << PTILE_SHIFT)) return 1;
+  if (mode == 2) return 8;
+  if (m < (1 << 20)) return 1;
+  if ((size_t)n * (size_t)(vbits / 8) < ((size_t)2 << 20)) return 1;
+  return 8;
+}
+
+GameLayout plan_layout(int32_t n, int64_t m, int vbits, size_t nblk, uint32_t nparts) {
   const size_t nn = (size_t)n, mm = (size_t)m, vb = (size_t)vbits / 8;
+  const bool pe = nparts > 1;
   const size_t sizes[L_N] = {4 * (nn + 1), 8 * mm, 4 * (nn + 1), 4 * mm, vb * nn, 2 * align_up(nn + 4), 4 * nn,
                              4 * nn, 8 * nn, 4 * C_WORDS, 8 * S_WORDS, 4 * ((nn + 31) / 32), 4 * nblk,
-                             8 * S_WORDS * nblk};
+                             8 * S_WORDS * nblk, pe ? 8 * mm : 0, pe ? 4 * partition_scratch_words(n, nparts) : 0,
+                             pe ? 4 * ((nn + 31) / 32) : 0, pe ? vb * nn * nparts : 0};
   GameLayout L{};
   for (int i = 0; i < L_N; i++) {
     L.off[i] = L.total;
@@ -273,7 +292,7 @@ GameLayout plan_layout(int32_t n, int64_t m, int vbits, size_t nblk) {
   return L;
 }
 
-void bind_layout(DevGame& dg, char* base, const GameLayout& L, int32_t n, int64_t m, int vbits) {
+void bind_layout(DevGame& dg, char* base, const GameLayout& L, int32_t n, int64_t m, int vbits, uint32_t nparts) {
   dg.n = n;
   dg.m = (uint32_t)m;
   dg.rs = (uint32_t*)(base + L.off[L_RS]);
@@ -291,6 +310,12 @@ void bind_layout(DevGame& dg, char* base, const GameLayout& L, int32_t n, int64_
   dg.blk_chg = (uint32_t*)(base + L.off[L_BLK]);
   dg.slots = (unsigned long long*)(base + L.off[L_SLOTS]);
   dg.vbits = vbits;
+  dg.nparts = nparts;
+  dg.part_size = (uint32_t)(((size_t)n + nparts - 1) / nparts);
+  dg.pedges = (const int2*)(base + L.off[L_PEDGES]);
+  dg.poff = (const uint32_t*)(base + L.off[L_POFF]);
+  dg.own_bits = (const uint32_t*)(base + L.off[L_OWNB]);
+  dg.part = base + L.off[L_PART];
 }
 
 size_t staging_bytes(int32_t n, int64_t m, bool host_inputs) {
@@ -339,8 +364,11 @@ hipError_t upload_game(const eg_game_desc* d, const HostPrep& prep, DevGame& dg,
                          (int2*)dg.edges, s)) != hipSuccess)
     return r;
   if (after_layout && (r = hipEventRecord(after_layout, s))) return r;
-  return launch_reverse_csr(dg.rs, dg.edges, d->n, (uint32_t)mm, (uint32_t*)dg.rev_off, (int32_t*)dg.rev_src,
-                            cursor, scan_tmp, scan_words, s);
+  if ((r = launch_reverse_csr(dg.rs, dg.edges, d->n, (uint32_t)mm, (uint32_t*)dg.rev_off, (int32_t*)dg.rev_src,
+                              cursor, scan_tmp, scan_words, s)) != hipSuccess)
+    return r;
+  if (dg.nparts > 1) return launch_partition(dg, d_own, cursor, scan_tmp, scan_words, s);
+  return hipSuccess;
 }
 
 int prepare(const eg_game_desc* desc, int bound_mode, hipStream_t s, HostPrep& prep, std::string* why) {
@@ -378,7 +406,9 @@ int eg_create(eg_ctx* ctx, const eg_game_desc* desc, eg_game** out, eg_stats* st
   const size_t nn = (size_t)g->n;
   const size_t nblk = (size_t)std::max(1, std::min<int>(ctx->grid, (int)((nn + eg::TILE_VERTICES - 1) / eg::TILE_VERTICES)));
   g->grid = (int)nblk;
-  const eg::GameLayout L = eg::plan_layout(g->n, g->m, g->vbits, nblk);
+  g->part_grid = std::max(8, ctx->grid / 8 * 8);
+  const uint32_t nparts = eg::choose_parts(g->n, g->m, g->vbits, ctx->cfg.partition);
+  const eg::GameLayout L = eg::plan_layout(g->n, g->m, g->vbits, nblk, nparts);
   hipError_t e = hipMalloc(&g->arena, L.total);
   if (e != hipSuccess) {
     game_free(g);
@@ -386,7 +416,7 @@ int eg_create(eg_ctx* ctx, const eg_game_desc* desc, eg_game** out, eg_stats* st
   }
   g->arena_bytes = L.total;
   eg::DevGame& dg = g->dg;
-  eg::bind_layout(dg, (char*)g->arena, L, g->n, g->m, g->vbits);
+  eg::bind_layout(dg, (char*)g->arena, L, g->n, g->m, g->vbits, nparts);
   g->out64 = (int64_t*)((char*)g->arena + L.off[eg::L_OUT]);
   dg.bound = g->bound;
   dg.top = g->bound + prep.clamp + 1;
@@ -469,7 +499,8 @@ int eg_solve_ex(eg_game* g, const eg_solve_opts* opts, int64_t* credits, eg_stat
   const eg::DevGame& dg = g->dg;
   const int grid = g->grid;
   const double t0 = now_s();
-  const uint64_t dense_at = std::max<uint64_t>(1, (uint64_t)g->n / 32);  // active vertices
+  const uint64_t dense_at = std::max<uint64_t>(1, (uint64_t)g->n / (ctx->cfg.dense_div ? ctx->cfg.dense_div : 32));
+  const uint64_t small_limit = ctx->cfg.small_limit ? (uint64_t)ctx->cfg.small_limit : eg::SMALL_LIMIT;
   HIPCHK(hipMemsetAsync(dg.ctrl, 0, 4 * eg::C_WORDS, s));
   HIPCHK(hipMemsetAsync(dg.slots, 0, 8 * eg::S_WORDS * (size_t)grid, s));
   HIPCHK(hipEventRecord(g->ev[0], s));
@@ -484,7 +515,7 @@ int eg_solve_ex(eg_game* g, const eg_solve_opts* opts, int64_t* credits, eg_stat
   // representation of the active set: a flag sweep for large sets, a list
   // for medium ones, and for small ones a single block running many rounds
   enum { SPARSE, DENSE, SMALL };
-  auto pick = [&](uint64_t size) { return size <= eg::SMALL_LIMIT ? SMALL : size >= dense_at ? DENSE : SPARSE; };
+  auto pick = [&](uint64_t size) { return size <= small_limit ? SMALL : size >= dense_at ? DENSE : SPARSE; };
   int mode = pick(active);
   if (active && mode != DENSE) HIPCHK(eg::launch_compact(dg, 1, grid, s));
   uint32_t batch = 2;
@@ -497,9 +528,16 @@ int eg_solve_ex(eg_game* g, const eg_solve_opts* opts, int64_t* credits, eg_stat
     if (max_rounds) allowed = std::min<uint64_t>(allowed, max_rounds - launched);
     HIPCHK(hipEventRecord(g->ev[3], s));
     if (mode == SMALL) {
-      HIPCHK(eg::launch_rounds_small(dg, g->vbits, r, (uint32_t)allowed, eg::SMALL_LIMIT, s));
+      HIPCHK(eg::launch_rounds_small(dg, g->vbits, r, (uint32_t)allowed, (uint32_t)small_limit, s));
     } else {
-      for (uint32_t j = 0; j < allowed; j++) HIPCHK(eg::launch_round(dg, g->vbits, g->h, mode == DENSE, r++, grid, s));
+      for (uint32_t j = 0; j < allowed; j++, r++) {
+        if (mode == DENSE && dg.nparts > 1) {
+          HIPCHK(eg::launch_partial(dg, g->vbits, r, g->part_grid, s));
+          HIPCHK(eg::launch_round_parts(dg, g->vbits, r, grid, s));
+        } else {
+          HIPCHK(eg::launch_round(dg, g->vbits, g->h, mode == DENSE, r, grid, s));
+        }
+      }
     }
     HIPCHK(hipEventRecord(g->ev[4], s));
     HIPCHK(hipMemcpyAsync(g->h_ctrl, dg.ctrl, 4 * eg::C_WORDS, hipMemcpyDeviceToHost, s));
@@ -525,7 +563,7 @@ int eg_solve_ex(eg_game* g, const eg_solve_opts* opts, int64_t* credits, eg_stat
       for (int b = 0; b < grid; b++) changed += g->h_blk[b];
       // predecessors of the changed vertices, at most
       const double est = (double)changed * g->avg_indeg;
-      if (est <= eg::SMALL_LIMIT) next_mode = SMALL;
+      if (est <= (double)small_limit) next_mode = SMALL;
       else if (est < (double)dense_at / 4) next_mode = SPARSE;
     } else {
       const uint64_t next = g->h_ctrl[eg::C_CNT0 + r % 3];

@@ -48,7 +48,17 @@ struct DevGame {
   int64_t bound;            // B
   int64_t top;              // device encoding of TOP: B + P + 1, P = largest stored weight
   int32_t vbits;            // 32 or 64: width of f
+  // target-partitioned copy of the edges for dense rounds (nparts > 1)
+  uint32_t nparts;          // slices of the vertex range (1 = no partitioned copy)
+  uint32_t part_size;       // vertices per slice
+  const int2* pedges;       // m: {target | tile-local source << 22, weight}, grouped by (tile, slice)
+  const uint32_t* poff;     // nchunks + 1: chunk (tile * nparts + slice) starts
+  const uint32_t* own_bits; // ceil(n/32): owner bits (1 = player 1)
+  void* part;               // nparts * n keys of width vbits (per-slice partial keys)
 };
+
+constexpr uint32_t PTILE = 1024;        // vertices per tile of the partitioned copy
+constexpr uint32_t PTILE_SHIFT = 22;    // tile-local source index sits above the 22 target bits
 
 // Slot states of the batched iteration.
 constexpr uint32_t SLOT_FREE = 0, SLOT_RUN = 1, SLOT_DONE = 2;
@@ -68,14 +78,22 @@ struct BatchTable {
 
 // Device layout of one game: every array in one allocation.
 enum LayoutPart : int {
-  L_RS, L_EDGES, L_ROFF, L_RSRC, L_F, L_ACT, L_WL0, L_WL1, L_OUT, L_CTRL, L_STATS, L_ACTBITS, L_BLK, L_SLOTS, L_N
+  L_RS, L_EDGES, L_ROFF, L_RSRC, L_F, L_ACT, L_WL0, L_WL1, L_OUT, L_CTRL, L_STATS, L_ACTBITS, L_BLK, L_SLOTS,
+  L_PEDGES, L_POFF, L_OWNB, L_PART, L_N
 };
 struct GameLayout {
   size_t off[L_N];
   size_t total;
 };
-GameLayout plan_layout(int32_t n, int64_t m, int vbits, size_t nblocks);
-void bind_layout(DevGame& dg, char* base, const GameLayout& L, int32_t n, int64_t m, int vbits);
+GameLayout plan_layout(int32_t n, int64_t m, int vbits, size_t nblocks, uint32_t nparts = 1);
+void bind_layout(DevGame& dg, char* base, const GameLayout& L, int32_t n, int64_t m, int vbits,
+                 uint32_t nparts = 1);
+uint32_t choose_parts(int32_t n, int64_t m, int vbits, int mode);
+hipError_t launch_partition(const DevGame& dg, const uint8_t* owner_bits, uint32_t* cursor, uint32_t* scan_tmp,
+                            size_t scan_words, hipStream_t s);
+size_t partition_scratch_words(int32_t n, uint32_t nparts);
+hipError_t launch_partial(const DevGame& g, int vbits, uint32_t r, int grid, hipStream_t s);
+hipError_t launch_round_parts(const DevGame& g, int vbits, uint32_t r, int grid, hipStream_t s);
 
 // Host-side preparation of a validated game.
 struct HostPrep {

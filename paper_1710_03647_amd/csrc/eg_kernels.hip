@@ -165,6 +165,72 @@ __global__ void k_scatter_preds(const uint32_t* rs, const int2* edges, int32_t n
   }
 }
 
+// ---------------------------------------------------------------- target-partitioned edge copy
+// For dense rounds of large games the gathers of f are confined per XCD: the
+// vertex range is cut into `nparts` slices, and a second copy of the edges is
+// grouped by (tile of PTILE source vertices, target slice).  Each record keeps
+// its target and its tile-local source index (10 bits above the 22 target
+// bits), so a chunk is reduced without knowing row boundaries.
+
+__device__ __forceinline__ uint32_t chunk_of(uint32_t v, uint32_t tgt, uint32_t nparts, uint32_t part_size) {
+  return (v / PTILE) * nparts + tgt / part_size;
+}
+
+template <bool SCATTER>
+__global__ void k_part_edges(const uint32_t* rs, const int2* edges, int32_t n, uint32_t m, uint32_t chunk,
+                             uint32_t nparts, uint32_t part_size, uint32_t* cnt, int2* pedges) {
+  const uint64_t first = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * chunk;
+  if (first >= m) return;
+  const uint32_t last = (uint32_t)std::min<uint64_t>(m, first + chunk);
+  int32_t v = source_of(rs, n, (uint32_t)first);
+  for (uint32_t e = (uint32_t)first; e < last; e++) {
+    while ((rs[v + 1] & ROW_MASK) <= e) v++;
+    const int2 ed = edges[e];
+    const uint32_t c = chunk_of((uint32_t)v, (uint32_t)ed.x, nparts, part_size);
+    if (SCATTER) {
+      const uint32_t slot = atomicAdd(&cnt[c], 1u);
+      pedges[slot] = make_int2((int32_t)((uint32_t)ed.x | (((uint32_t)v % PTILE) << PTILE_SHIFT)), ed.y);
+    } else {
+      atomicAdd(&cnt[c], 1u);
+    }
+  }
+}
+
+__global__ void k_owner_words(const uint32_t* rs, int32_t n, uint32_t* own) {
+  const uint32_t words = ((uint32_t)n + 31) / 32;
+  for (uint32_t w = blockIdx.x * blockDim.x + threadIdx.x; w < words; w += gridDim.x * blockDim.x) {
+    uint32_t x = 0;
+    for (uint32_t i = 0; i < 32 && w * 32 + i < (uint32_t)n; i++) x |= (rs[w * 32 + i] >> 31) << i;
+    own[w] = x;
+  }
+}
+
+size_t partition_scratch_words(int32_t n, uint32_t nparts) {
+  return (size_t)(((uint32_t)n + PTILE - 1) / PTILE) * nparts + 1;
+}
+
+hipError_t launch_partition(const DevGame& dg, const uint8_t*, uint32_t* cursor, uint32_t* scan_tmp,
+                            size_t scan_words, hipStream_t s) {
+  const uint32_t nchunks = (uint32_t)partition_scratch_words(dg.n, dg.nparts) - 1;
+  // the chunk counters reuse the n + 1 words of the predecessor-list cursor
+  if (nchunks > (uint32_t)dg.n || scan_words < scan_tmp_words((size_t)nchunks + 1)) return hipErrorInvalidValue;
+  hipError_t e = hipMemsetAsync(cursor, 0, 4 * ((size_t)nchunks + 1), s);
+  if (e != hipSuccess) return e;
+  const uint32_t chunk = 16;
+  const int grid_s = (int)std::max<uint64_t>(1, ((uint64_t)dg.m + (uint64_t)chunk * BLOCK - 1) / ((uint64_t)chunk * BLOCK));
+  hipLaunchKernelGGL(k_part_edges<false>, dim3(grid_s), dim3(BLOCK), 0, s, dg.rs, dg.edges, dg.n, dg.m, chunk,
+                     dg.nparts, dg.part_size, cursor, (int2*)nullptr);
+  e = exclusive_scan(cursor, (uint32_t*)dg.poff, (size_t)nchunks + 1, scan_tmp, s);
+  if (e != hipSuccess) return e;
+  e = hipMemcpyAsync(cursor, dg.poff, 4 * (size_t)nchunks, hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_part_edges<true>, dim3(grid_s), dim3(BLOCK), 0, s, dg.rs, dg.edges, dg.n, dg.m, chunk,
+                     dg.nparts, dg.part_size, cursor, (int2*)dg.pedges);
+  const int grid_w = (int)std::max<int64_t>(1, std::min<int64_t>((((int64_t)dg.n + 31) / 32 + BLOCK - 1) / BLOCK, 4096));
+  hipLaunchKernelGGL(k_owner_words, dim3(grid_w), dim3(BLOCK), 0, s, dg.rs, dg.n, (uint32_t*)dg.own_bits);
+  return hipGetLastError();
+}
+
 hipError_t launch_reverse_csr(const uint32_t* rs, const int2* edges, int32_t n, uint32_t m,
                               uint32_t* rev_off, int32_t* rev_src, uint32_t* cursor,
                               uint32_t* scan_tmp, size_t scan_tmp_words_avail, hipStream_t s) {
@@ -375,7 +441,7 @@ struct Counters {
 // flattened the same way.  Any degree distribution is balanced across the
 // block.  Returns with the shared arrays still in use: the caller
 // synchronises before the next tile.
-template <typename V, bool DENSE>
+template <typename V, bool DENSE, bool PART = false>
 __device__ __forceinline__ void round_tile(const DevGame& g, RoundShared<V>& sh, uint32_t r, uint32_t t,
                                            uint32_t items, Counters& c) {
   const uint32_t tid = threadIdx.x;
@@ -409,10 +475,20 @@ __device__ __forceinline__ void round_tile(const DevGame& g, RoundShared<V>& sh,
   if (tid == BLOCK - 1) sh.epre[BLOCK] = E;
   sh.ebeg[tid] = raw;
   sh.key[tid] = (raw & OWNER_BIT) ? V(0) : std::numeric_limits<V>::max();
+  if (PART && v >= 0) {
+    // the slices' partial keys of v, computed by k_partial
+    V k = sh.key[tid];
+    const V* part = (const V*)g.part;
+    for (uint32_t q = 0; q < g.nparts; q++) {
+      const V y = part[(size_t)q * (uint32_t)g.n + (uint32_t)v];
+      k = y < k ? y : k;
+    }
+    sh.key[tid] = k;
+  }
   __syncthreads();
   if (E == 0) return;  // block-uniform: no active vertex in this tile
 
-  for (uint32_t x0 = 0; x0 < E; x0 += BLOCK * UNROLL) {
+  for (uint32_t x0 = 0; x0 < (PART ? 0u : E); x0 += BLOCK * UNROLL) {
     uint32_t slot[UNROLL];
     int2 ed[UNROLL];
     V fu[UNROLL];
@@ -476,6 +552,63 @@ __device__ __forceinline__ void round_tile(const DevGame& g, RoundShared<V>& sh,
   }
 }
 
+// Partial keys of every vertex of a tile over the targets of one slice, for a
+// dense round that reads the partitioned edge copy.  Block b works on the
+// slices of XCD b % 8 (workgroups are dealt to the XCDs in turn), so each
+// XCD gathers f only from its own slices, which stay in its L2.  Keys are
+// computed for all vertices of the tile; the combining round uses those of
+// active vertices only.
+template <typename V>
+__global__ __launch_bounds__(BLOCK) void k_partial(DevGame g, uint32_t r) {
+  __shared__ V key[PTILE];
+  __shared__ uint32_t own[PTILE / 32];
+  if (g.ctrl[C_ANY0 + (r - 1) % 3] == 0) return;  // L_r is empty
+  const V* f = (const V*)g.f;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t n = (uint32_t)g.n, nparts = g.nparts;
+  const uint32_t ntiles = (n + PTILE - 1) / PTILE;
+  const uint32_t xcd = blockIdx.x % 8, lb = blockIdx.x / 8, nlb = gridDim.x / 8;
+  const uint32_t per_xcd = nparts / 8;
+  const uint32_t items = ntiles * per_xcd;
+  const uint32_t nwords = (n + 31) / 32;
+  for (uint32_t i = lb; i < items; i += nlb) {
+    const uint32_t tile = i / per_xcd, q = xcd + 8 * (i % per_xcd);
+    const uint32_t v0 = tile * PTILE;
+    __syncthreads();
+    for (uint32_t j = tid; j < PTILE / 32; j += BLOCK) own[j] = v0 / 32 + j < nwords ? g.own_bits[v0 / 32 + j] : 0u;
+    __syncthreads();
+    for (uint32_t j = tid; j < PTILE; j += BLOCK)
+      key[j] = ((own[j >> 5] >> (j & 31)) & 1u) ? V(0) : std::numeric_limits<V>::max();
+    __syncthreads();
+    const uint32_t c = tile * nparts + q;
+    const uint32_t beg = g.poff[c], end = g.poff[c + 1];
+    for (uint32_t x0 = beg; x0 < end; x0 += BLOCK * UNROLL) {
+      int2 ed[UNROLL];
+      V fu[UNROLL];
+#pragma unroll
+      for (int j = 0; j < UNROLL; j++) {
+        const uint32_t x = x0 + j * BLOCK + tid;
+        if (x < end) ed[j] = g.pedges[x];
+      }
+#pragma unroll
+      for (int j = 0; j < UNROLL; j++)
+        if (x0 + j * BLOCK + tid < end) fu[j] = f[(uint32_t)ed[j].x & ((1u << PTILE_SHIFT) - 1)];
+#pragma unroll
+      for (int j = 0; j < UNROLL; j++)
+        if (x0 + j * BLOCK + tid < end) {
+          const uint32_t loc = (uint32_t)ed[j].x >> PTILE_SHIFT;
+          V tm = fu[j] - (V)ed[j].y;
+          tm = tm > V(0) ? tm : V(0);
+          __hip_atomic_fetch_min(&key[loc], ((own[loc >> 5] >> (loc & 31)) & 1u) ? -tm : tm, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+    }
+    __syncthreads();
+    V* part = (V*)g.part + (size_t)q * n;
+    for (uint32_t j = tid; j < PTILE && v0 + j < n; j += BLOCK) part[v0 + j] = key[j];
+  }
+}
+
 // Sum the counters of the block into LDS (sh.st must be zero on entry).
 template <typename V>
 __device__ __forceinline__ void block_counters(RoundShared<V>& sh, const Counters& c) {
@@ -489,7 +622,7 @@ __device__ __forceinline__ void block_counters(RoundShared<V>& sh, const Counter
 
 // One round of Alg. 3 over L_r of one game: blocks take the tiles of the
 // active set in turn (see round_tile).
-template <typename V, bool DENSE>
+template <typename V, bool DENSE, bool PART = false>
 __global__ __launch_bounds__(BLOCK) void k_round(DevGame g, uint32_t r) {
   __shared__ RoundShared<V> sh;
   const uint32_t tid = threadIdx.x;
@@ -511,7 +644,7 @@ __global__ __launch_bounds__(BLOCK) void k_round(DevGame g, uint32_t r) {
   const uint32_t ntiles = (items + TILE - 1) / TILE;
   for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     __syncthreads();  // the previous tile is done with the shared arrays
-    round_tile<V, DENSE>(g, sh, r, t, items, c);
+    round_tile<V, DENSE, PART>(g, sh, r, t, items, c);
   }
   block_counters(sh, c);
   if (!DENSE) {
@@ -762,6 +895,18 @@ hipError_t launch_round(const DevGame& g, int vbits, int h, bool dense, uint32_t
     if (dense) hipLaunchKernelGGL((k_round<int64_t, true>), dim3(grid), dim3(BLOCK), 0, s, g, r);
     else hipLaunchKernelGGL((k_round<int64_t, false>), dim3(grid), dim3(BLOCK), 0, s, g, r);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_partial(const DevGame& g, int vbits, uint32_t r, int grid, hipStream_t s) {
+  if (vbits == 32) hipLaunchKernelGGL(k_partial<int32_t>, dim3(grid), dim3(BLOCK), 0, s, g, r);
+  else hipLaunchKernelGGL(k_partial<int64_t>, dim3(grid), dim3(BLOCK), 0, s, g, r);
+  return hipGetLastError();
+}
+
+hipError_t launch_round_parts(const DevGame& g, int vbits, uint32_t r, int grid, hipStream_t s) {
+  if (vbits == 32) hipLaunchKernelGGL((k_round<int32_t, true, true>), dim3(grid), dim3(BLOCK), 0, s, g, r);
+  else hipLaunchKernelGGL((k_round<int64_t, true, true>), dim3(grid), dim3(BLOCK), 0, s, g, r);
   return hipGetLastError();
 }
 

@@ -1,0 +1,130 @@
+"""Autotuner for the launch shape of the round kernels.
+
+The round driver has four knobs (eg_config): resident blocks per compute unit,
+the active-set size above which rounds sweep flags instead of a list
+(n / dense_div), the size below which one block runs many rounds
+(small_limit), and whether dense rounds read the target-sliced edge copy
+(partition).  Which setting is fastest depends on the graph class: its size,
+its degree and its value width.
+
+`tune(game)` times candidate settings on a proxy of the game's class (the
+same generator at 1/16 of the vertices when the game came from `synth`, else
+the game itself under a round budget) and stores the winner in a JSON table
+keyed by GPU architecture and graph class.  `config_for(game)` returns the
+stored setting, or the library defaults.  The credits never depend on these
+choices; only time does.
+
+Usage: python -m paper_1710_03647_amd.tune uniform   (tunes the uniform game's class)
+"""
+from __future__ import annotations
+
+import itertools
+import json
+import math
+import os
+import sys
+import time
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+TABLE = os.path.join(PKG, "tuning.json")
+
+DEFAULTS = {"blocks_per_cu": 8, "dense_div": 32, "small_limit": 1024, "partition": 0}
+SPACE = {
+    "blocks_per_cu": [4, 8],
+    "dense_div": [8, 32],
+    "small_limit": [512, 1024, 4096],
+    "partition": [0, 1],
+}
+
+
+def graph_class(n: int, m: int, value_bits: int) -> str:
+    """Coarse class of a game: log2 buckets of n and of the average degree, value width."""
+    nb = int(math.log2(max(n, 1)))
+    db = int(math.log2(max(m / max(n, 1), 1)))
+    return f"n2^{nb}-d2^{db}-v{value_bits}"
+
+
+def arch(device: int = 0) -> str:
+    try:
+        import torch
+
+        return torch.cuda.get_device_properties(device).gcnArchName.split(":")[0]
+    except Exception:
+        return "gfx950"
+
+
+def load_table(path: str = TABLE) -> dict:
+    if os.path.exists(path):
+        with open(path) as fh:
+            return json.load(fh)
+    return {}
+
+
+def config_for(game, device: int = 0, path: str = TABLE) -> dict:
+    """Stored launch shape for the game's class (defaults if untuned)."""
+    from . import eg
+
+    info = eg.check(game)
+    key = f"{arch(device)}:{graph_class(info['n'], info['m'], info['value_bits'])}"
+    entry = load_table(path).get(key)
+    return dict(entry["config"]) if entry else dict(DEFAULTS)
+
+
+def _proxy(game):
+    from . import synth
+
+    meta = getattr(game, "meta", {}) or {}
+    if meta.get("kind") == "uniform" and game.n >= 1 << 14:
+        return synth.gen_uniform(game.n // 16, meta["deg"], meta["wlim"], meta["seed"]), 0
+    if meta.get("kind") == "rmat" and meta.get("scale", 0) >= 14:
+        return synth.gen_rmat(meta["scale"] - 4, meta["edge_factor"], wlim=meta["wlim"], seed=meta["seed"]), 0
+    return game, 2000
+
+
+def _time(game, cfg: dict, max_rounds: int, device: int) -> float:
+    from . import eg
+
+    with eg.Context(device, **cfg) as ctx:
+        with ctx.create(game) as g:
+            g.solve(max_rounds=min(max_rounds, 50) if max_rounds else 50, allow_timeout=True)  # warm
+            t0 = time.perf_counter()
+            g.solve(max_rounds=max_rounds, allow_timeout=True)
+            return time.perf_counter() - t0
+
+
+def tune(game, device: int = 0, path: str = TABLE, space: dict | None = None, verbose: bool = True) -> dict:
+    """Time every candidate on the proxy, store and return the fastest."""
+    from . import eg
+
+    space = space or SPACE
+    proxy, rounds = _proxy(game)
+    info = eg.check(game)
+    key = f"{arch(device)}:{graph_class(info['n'], info['m'], info['value_bits'])}"
+    results = []
+    names = list(space)
+    for values in itertools.product(*(space[k] for k in names)):
+        cfg = dict(zip(names, values))
+        t = _time(proxy, cfg, rounds, device)
+        results.append((t, cfg))
+        if verbose:
+            print(f"[tune] {key} {cfg}: {t * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    results.sort(key=lambda x: x[0])
+    best_t, best = results[0]
+    table = load_table(path)
+    table[key] = {"config": best, "proxy_seconds": best_t,
+                  "default_seconds": next((t for t, c in results if c == DEFAULTS), None),
+                  "proxy": getattr(proxy, "name", ""), "rounds": rounds or "to the fixpoint"}
+    with open(path, "w") as fh:
+        json.dump(table, fh, indent=1, sort_keys=True)
+    return best
+
+
+if __name__ == "__main__":
+    sys.path.insert(0, os.path.dirname(PKG))
+    from paper_1710_03647_amd import synth
+
+    which = sys.argv[1:] or ["uniform"]
+    for w in which:
+        g = {"uniform": synth.gen_uniform_full, "rmat": synth.gen_rmat_full, "plain": synth.gen_plain,
+             "torus": lambda: synth.gen_torus(256, seed=4)}[w]()
+        print(w, tune(g))

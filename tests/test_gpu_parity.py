@@ -173,3 +173,42 @@ def test_set_measure_rejects_out_of_range(ctx):
         assert ei.value.code == eg.EG_EINVAL
     finally:
         g.destroy()
+
+
+PARTITIONED = [
+    ("uniform-20k", lambda: synth.gen_uniform(20000, 16, 1000, 2)),
+    ("uniform-ragged-int32", lambda: synth.gen_uniform(12345, 7, 300, 21)),
+    ("rmat-13-int64", lambda: synth.gen_rmat(13, 16, wlim=400000, seed=5)),
+    ("rmat-14", lambda: synth.gen_rmat(14, 16, seed=3)),
+    ("torus-40", lambda: synth.gen_torus(40, seed=4)),
+]
+
+
+@pytest.mark.parametrize("name,make", PARTITIONED, ids=[s[0] for s in PARTITIONED])
+def test_partitioned_dense_rounds(oracle_mod, name, make):
+    """Dense rounds over the target-sliced edge copy (forced on small games)."""
+    game = make()
+    with eg.Context(0, partition=2) as c:
+        f, st = gpu_solve(c, game)
+    assert st["dense_rounds"] > 0
+    pins.expect_equal(f, oracle_mod.solve(game).f, name)
+
+
+@pytest.mark.parametrize("name,make", PARTITIONED[:4], ids=[s[0] for s in PARTITIONED[:4]])
+def test_partitioned_round_is_one_jacobi_step(oracle_mod, name, make):
+    """A partitioned dense round reads only the values of the previous round:
+    from any measure below the fixpoint, one resumed round with every vertex
+    active is exactly one application of the lifting operator everywhere."""
+    game = make()
+    want = oracle_mod.solve(game)
+    noise = synth.to_int(synth.draws(11, 2, 0, game.n), 0, 4 * game.W)
+    f0 = np.minimum(want.f, noise)
+    with eg.Context(0, partition=2) as c:
+        g = c.create(game)
+        try:
+            g.set_measure(f0)
+            f1, st, rc = g.solve(max_rounds=1, resume=True, allow_timeout=True)
+        finally:
+            g.destroy()
+    assert st["dense_rounds"] == 1
+    pins.expect_equal(f1, pins.lift_all_numpy(game, f0, want.bound), name)
