@@ -179,7 +179,11 @@ def main():
     info = eg.check(game)
     log(f"[bench] {desc}: n={game.n} m={game.m} bound={info['bound']} value_bits={info['value_bits']}")
 
-    ctx = eg.Context(0, stream=stream)
+    from paper_1710_03647_amd import tune
+
+    shape = tune.config_for(game)
+    log(f"[bench] launch shape: {shape}")
+    ctx = eg.Context(0, stream=stream, **shape)
     # kernels loaded once, untimed (a small game)
     from paper_1710_03647_amd import synth
 
@@ -235,7 +239,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "n": game.n, "m": game.m, "W": game.W, "bound": info["bound"],
                    "mode": "full-frontier lift rounds" if args.sweep else "solve to fixpoint",
-                   "rounds_per_step": agg["rounds"] / steps},
+                   "rounds_per_step": agg["rounds"] / steps, "launch_shape": shape},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
                      "kernel": "k_round (lift + predecessor activation, one launch per round)",
