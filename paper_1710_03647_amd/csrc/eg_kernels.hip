@@ -18,6 +18,15 @@ constexpr int BLOCK = 256;
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
+// Block barrier that first waits until this wave's LDS operations, atomics
+// included, have completed (s_waitcnt lgkmcnt(0)).  The workgroup fence of
+// __syncthreads() may leave that wait out, and then an LDS atomic issued
+// before the barrier can land after another wave's read that follows it.
+__device__ __forceinline__ void block_sync() {
+  __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt = 0; vmcnt, expcnt unconstrained
+  __syncthreads();
+}
+
 // number of set bits of mask in lanes below this one
 __device__ __forceinline__ uint32_t mbcnt(unsigned long long mask) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
@@ -81,7 +90,7 @@ __device__ __forceinline__ uint32_t block_inclusive_scan(uint32_t x) {
     if (lane >= (uint32_t)o) x += y;
   }
   if (lane == WAVE - 1) wsum[wid] = x;
-  __syncthreads();
+  block_sync();
   if (wid == 0) {
     uint32_t t = lane < SCAN_BLOCK / WAVE ? wsum[lane] : 0u;
 #pragma unroll
@@ -91,7 +100,7 @@ __device__ __forceinline__ uint32_t block_inclusive_scan(uint32_t x) {
     }
     if (lane < SCAN_BLOCK / WAVE) wsum[lane] = t;
   }
-  __syncthreads();
+  block_sync();
   return x + (wid > 0 ? wsum[wid - 1] : 0u);
 }
 
@@ -298,7 +307,7 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t* wsum, 
     if (lane >= (uint32_t)o) incl += y;
   }
   if (lane == WAVE - 1) wsum[wid] = incl;
-  __syncthreads();
+  block_sync();
   uint32_t off = 0, tot = 0;
 #pragma unroll
   for (int w = 0; w < BLOCK / WAVE; w++) {
@@ -381,7 +390,7 @@ template <typename V>
 __global__ __launch_bounds__(BLOCK) void k_init(DevGame g, int resume) {
   __shared__ uint32_t s_cnt;
   if (threadIdx.x == 0) s_cnt = 0;
-  __syncthreads();
+  block_sync();
   V* f = (V*)g.f;
   uint32_t mine = 0;
   for (uint32_t v = blockIdx.x * BLOCK + threadIdx.x; v < (uint32_t)g.n; v += gridDim.x * BLOCK) {
@@ -392,7 +401,7 @@ __global__ __launch_bounds__(BLOCK) void k_init(DevGame g, int resume) {
     mine += act;
   }
   atomicAdd(&s_cnt, mine);
-  __syncthreads();
+  block_sync();
   if (threadIdx.x == 0) {
     g.blk_chg[blockIdx.x] = s_cnt;
     if (s_cnt) g.ctrl[C_ANY0 + 0] = 1;
@@ -406,20 +415,20 @@ __global__ __launch_bounds__(BLOCK) void k_compact(DevGame g, uint32_t r) {
   int32_t* wl = (r & 1) ? g.wl1 : g.wl0;
   uint32_t* cnt = &g.ctrl[C_CNT0 + r % 3];
   if (threadIdx.x == 0) nb = 0;
-  __syncthreads();
+  block_sync();
   const uint32_t ntiles = ((uint32_t)g.n + TILE - 1) / TILE;
   for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const uint32_t v = t * TILE + threadIdx.x;
     lds_append(v < (uint32_t)g.n && ((r & 1) ? g.act1 : g.act0)[v] != 0, (int32_t)v, buf, &nb);
-    __syncthreads();
+    block_sync();
     if (nb > PUSH_CAP - TILE || t + gridDim.x >= ntiles) {
       if (threadIdx.x == 0) base = nb ? atomicAdd(cnt, nb) : 0;
-      __syncthreads();
+      block_sync();
       for (uint32_t i = threadIdx.x; i < nb; i += BLOCK) wl[base + i] = buf[i];
-      __syncthreads();
+      block_sync();
       if (threadIdx.x == 0) nb = 0;
     }
-    __syncthreads();
+    block_sync();
   }
 }
 
@@ -485,7 +494,7 @@ __device__ __forceinline__ void round_tile(const DevGame& g, RoundShared<V>& sh,
     }
     sh.key[tid] = k;
   }
-  __syncthreads();
+  block_sync();
   if (E == 0) return;  // block-uniform: no active vertex in this tile
 
   for (uint32_t x0 = 0; x0 < (PART ? 0u : E); x0 += BLOCK * UNROLL) {
@@ -514,7 +523,7 @@ __device__ __forceinline__ void round_tile(const DevGame& g, RoundShared<V>& sh,
                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
       }
   }
-  __syncthreads();
+  block_sync();
 
   uint32_t ideg = 0;
   if (v >= 0) {
@@ -535,7 +544,7 @@ __device__ __forceinline__ void round_tile(const DevGame& g, RoundShared<V>& sh,
   if (tid == BLOCK - 1) sh.ppre[BLOCK] = P;
   sh.pbeg[tid] = pb;
   c.scanned += ideg;
-  __syncthreads();
+  block_sync();
   for (uint32_t x0 = 0; x0 < P; x0 += BLOCK * UNROLL) {
     int32_t pr[UNROLL];
 #pragma unroll
@@ -574,12 +583,12 @@ __global__ __launch_bounds__(BLOCK) void k_partial(DevGame g, uint32_t r) {
   for (uint32_t i = lb; i < items; i += nlb) {
     const uint32_t tile = i / per_xcd, q = xcd + 8 * (i % per_xcd);
     const uint32_t v0 = tile * PTILE;
-    __syncthreads();
+    block_sync();
     for (uint32_t j = tid; j < PTILE / 32; j += BLOCK) own[j] = v0 / 32 + j < nwords ? g.own_bits[v0 / 32 + j] : 0u;
-    __syncthreads();
+    block_sync();
     for (uint32_t j = tid; j < PTILE; j += BLOCK)
       key[j] = ((own[j >> 5] >> (j & 31)) & 1u) ? V(0) : std::numeric_limits<V>::max();
-    __syncthreads();
+    block_sync();
     const uint32_t c = tile * nparts + q;
     const uint32_t beg = g.poff[c], end = g.poff[c + 1];
     for (uint32_t x0 = beg; x0 < end; x0 += BLOCK * UNROLL) {
@@ -603,7 +612,7 @@ __global__ __launch_bounds__(BLOCK) void k_partial(DevGame g, uint32_t r) {
                                  __HIP_MEMORY_SCOPE_WORKGROUP);
         }
     }
-    __syncthreads();
+    block_sync();
     V* part = (V*)g.part + (size_t)q * n;
     for (uint32_t j = tid; j < PTILE && v0 + j < n; j += BLOCK) part[v0 + j] = key[j];
   }
@@ -617,7 +626,7 @@ __device__ __forceinline__ void block_counters(RoundShared<V>& sh, const Counter
   atomicAdd(&sh.st[S_CHANGES], c.changes);
   atomicAdd(&sh.st[S_PUSHES], c.pushes);
   atomicAdd(&sh.st[S_SCANNED], c.scanned);
-  __syncthreads();
+  block_sync();
 }
 
 // One round of Alg. 3 over L_r of one game: blocks take the tiles of the
@@ -643,7 +652,7 @@ __global__ __launch_bounds__(BLOCK) void k_round(DevGame g, uint32_t r) {
   Counters c;
   const uint32_t ntiles = (items + TILE - 1) / TILE;
   for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    __syncthreads();  // the previous tile is done with the shared arrays
+    block_sync();  // the previous tile is done with the shared arrays
     round_tile<V, DENSE, PART>(g, sh, r, t, items, c);
   }
   block_counters(sh, c);
@@ -652,7 +661,7 @@ __global__ __launch_bounds__(BLOCK) void k_round(DevGame g, uint32_t r) {
     int32_t* wl_out = (r & 1) ? g.wl0 : g.wl1;
     const uint32_t nf = sh.n_push < (uint32_t)PUSH_CAP ? sh.n_push : (uint32_t)PUSH_CAP;
     if (tid == 0) sh.base = nf ? atomicAdd(cnt_out, nf) : 0u;
-    __syncthreads();
+    block_sync();
     for (uint32_t i = tid; i < nf; i += BLOCK) wl_out[sh.base + i] = sh.push[i];
   }
   if (tid < S_WORDS) g.slots[blockIdx.x * S_WORDS + tid] += sh.st[tid];
@@ -679,7 +688,7 @@ __global__ __launch_bounds__(BLOCK) void k_rounds_small(DevGame g, uint32_t r0, 
   Counters c;
   uint32_t r = r0;
   for (uint32_t k = 0; k < max_rounds; k++, r++) {
-    __syncthreads();
+    block_sync();
     if (tid == 0) {
       const uint32_t items = g.ctrl[C_CNT0 + r % 3];
       s_items = items;
@@ -691,26 +700,26 @@ __global__ __launch_bounds__(BLOCK) void k_rounds_small(DevGame g, uint32_t r0, 
         g.ctrl[C_ROUNDS] += 1;
       }
     }
-    __syncthreads();
+    block_sync();
     const uint32_t items = s_items;
     if (items == 0 || items > limit) break;
     const unsigned long long before = c.changes;
     const uint32_t ntiles = (items + TILE - 1) / TILE;
     for (uint32_t t = 0; t < ntiles; t++) {
-      __syncthreads();
+      block_sync();
       round_tile<V, false>(g, sh, r, t, items, c);
     }
-    __syncthreads();
+    block_sync();
     if (c.changes != before) s_changed = 1;
     uint32_t* cnt_out = &g.ctrl[C_CNT0 + (r + 1) % 3];
     int32_t* wl_out = (r & 1) ? g.wl0 : g.wl1;
     const uint32_t nf = sh.n_push < (uint32_t)PUSH_CAP ? sh.n_push : (uint32_t)PUSH_CAP;
     if (tid == 0) sh.base = nf ? atomicAdd(cnt_out, nf) : 0u;
-    __syncthreads();
+    block_sync();
     for (uint32_t i = tid; i < nf; i += BLOCK) wl_out[sh.base + i] = sh.push[i];
     if (tid == 0 && s_changed) g.ctrl[C_ANY0 + r % 3] = 1;
   }
-  __syncthreads();
+  block_sync();
   block_counters(sh, c);
   if (tid < S_WORDS) g.slots[tid] += sh.st[tid];
   if (tid == 0) g.ctrl[C_NEXT] = r;
@@ -740,7 +749,7 @@ __global__ __launch_bounds__(1024) void k_plan(BatchTable bt) {
   const uint32_t tid = threadIdx.x;
   const uint32_t epoch = bt.ctl[B_EPOCH] + 1;
   if (tid == 0) carry = 0;
-  __syncthreads();
+  block_sync();
   for (uint32_t base = 0; base < bt.nslots; base += 1024) {
     const uint32_t s = base + tid;
     uint32_t tasks = 0;
@@ -764,16 +773,16 @@ __global__ __launch_bounds__(1024) void k_plan(BatchTable bt) {
       if (lane >= (uint32_t)o) incl += y;
     }
     if (lane == WAVE - 1) wsum[wid] = incl;
-    __syncthreads();
+    block_sync();
     uint32_t off = carry, tot = 0;
     for (int w = 0; w < 1024 / WAVE; w++) {
       off += (uint32_t)w < wid ? wsum[w] : 0u;
       tot += wsum[w];
     }
     if (s < bt.nslots) bt.task_begin[s] = off + incl - tasks;
-    __syncthreads();
+    block_sync();
     if (tid == 0) carry += tot;
-    __syncthreads();
+    block_sync();
   }
   if (tid == 0) {
     bt.task_begin[bt.nslots] = carry;
@@ -801,7 +810,7 @@ __device__ __forceinline__ void batch_task(const BatchTable& bt, RoundShared<V>&
   if (threadIdx.x < S_WORDS) sh.st[threadIdx.x] = 0;
   Counters c;
   round_tile<V, true>(g, sh, r, t, (uint32_t)g.n, c);
-  __syncthreads();
+  block_sync();
   block_counters(sh, c);
   if (threadIdx.x < S_WORDS && sh.st[threadIdx.x]) atomicAdd(&bt.st[s * S_WORDS + threadIdx.x], sh.st[threadIdx.x]);
   if (threadIdx.x == 0 && sh.st[S_CHANGES]) g.ctrl[C_ANY0 + r % 3] = 1;
@@ -812,7 +821,7 @@ __global__ __launch_bounds__(BLOCK) void k_batch_round(BatchTable bt) {
   const uint32_t ntasks = bt.ctl[B_TASKS];
   const uint32_t epoch = bt.ctl[B_EPOCH];
   for (uint32_t x = blockIdx.x; x < ntasks; x += gridDim.x) {
-    __syncthreads();
+    block_sync();
     const uint32_t s = find_slot(bt.task_begin, bt.nslots, x);
     const uint32_t t = x - bt.task_begin[s];
     if (bt.games[s].top <= INT32_MAX)  // 32-bit values (see the value width rule)
@@ -832,10 +841,10 @@ hipError_t launch_epoch(const BatchTable& bt, int grid, hipStream_t s) {
 __global__ void k_reduce_slots(DevGame g, uint32_t nblocks) {
   __shared__ unsigned long long acc[S_WORDS];
   if (threadIdx.x < S_WORDS) acc[threadIdx.x] = 0;
-  __syncthreads();
+  block_sync();
   for (uint32_t b = threadIdx.x; b < nblocks; b += blockDim.x)
     for (int k = 0; k < S_WORDS; k++) atomicAdd(&acc[k], g.slots[b * S_WORDS + k]);
-  __syncthreads();
+  block_sync();
   if (threadIdx.x < S_WORDS) g.stats[threadIdx.x] = acc[threadIdx.x];
 }
 

@@ -208,6 +208,38 @@ def lift_all_numpy(game, f, bound):
     return np.where(game.owner == 0, mn, mx)
 
 
+
+def initially_active_numpy(game):
+    """L_1 of Alg. 3: player-0 vertices whose out-edges are all negative,
+    player-1 vertices with some negative out-edge."""
+    src = np.repeat(np.arange(game.n), np.diff(game.off))
+    neg = np.bincount(src, weights=(game.w < 0), minlength=game.n)
+    deg = np.diff(game.off)
+    return np.where(game.owner == 0, neg == deg, neg > 0)
+
+
+def synchronous_rounds_numpy(game, bound):
+    """Alg. 3 with synchronous rounds: round r lifts every vertex of L_r from the
+    values left by round r-1, and L_{r+1} holds the predecessors of the vertices
+    whose value changed.  Returns (f, rounds, lifts, changes, relaxed edges)."""
+    src = np.repeat(np.arange(game.n), np.diff(game.off))
+    deg = np.diff(game.off).astype(np.int64)
+    f = np.zeros(game.n, dtype=np.int64)
+    act = initially_active_numpy(game)
+    rounds = lifts = changes = edges = 0
+    while act.any():
+        new = lift_all_numpy(game, f, bound)
+        changed = act & (new != f)
+        f = np.where(act, new, f)
+        rounds += 1
+        lifts += int(act.sum())
+        changes += int(changed.sum())
+        edges += int(deg[act].sum())
+        act = np.zeros(game.n, dtype=bool)
+        act[src[changed[game.tgt]]] = True
+    return f, rounds, lifts, changes, edges
+
+
 def pin_fixpoint(game, f, bound, what=""):
     """I1 and I2: f is a fixpoint, finite values lie in [0, bound]."""
     f = np.asarray(f, dtype=np.int64)

@@ -212,3 +212,26 @@ def test_partitioned_round_is_one_jacobi_step(oracle_mod, name, make):
             g.destroy()
     assert st["dense_rounds"] == 1
     pins.expect_equal(f1, pins.lift_all_numpy(game, f0, want.bound), name)
+
+
+SYNCHRONOUS = [
+    ("rmat-11", lambda: synth.gen_rmat(11, 16, seed=3)),
+    ("rmat-11-int64", lambda: synth.gen_rmat(11, 16, wlim=2_000_000, seed=3)),
+    ("uniform-3000", lambda: synth.gen_uniform(3000, 4, 30, 9)),
+]
+
+
+@pytest.mark.parametrize("name,make", SYNCHRONOUS, ids=[s[0] for s in SYNCHRONOUS])
+def test_partitioned_rounds_are_synchronous(oracle_mod, name, make):
+    """With every round a target-sliced dense round, the solve is Alg. 3 with
+    synchronous rounds: the same lifts, changes and relaxed edges as the numpy
+    iteration, round for round.  A slice key that missed an edge (an LDS update
+    not yet visible to the wave that stores the key) changes these counts."""
+    game = make()
+    want = oracle_mod.solve(game)
+    f_np, rounds, lifts, changes, edges = pins.synchronous_rounds_numpy(game, want.bound)
+    with eg.Context(0, partition=2, dense_div=1 << 20, small_limit=1) as c:
+        f, st = gpu_solve(c, game)
+    pins.expect_equal(f, want.f, name)
+    assert st["dense_rounds"] >= st["rounds"] >= rounds
+    assert (st["lifts"], st["changes"], st["relaxed_edges"]) == (lifts, changes, edges)

@@ -111,3 +111,14 @@ def test_plain_config_summary(oracle_mod):
     r = oracle_mod.solve(g)
     assert r.status == 0 and r.bound == 9990
     pins.pin_fixpoint(g, r.f, r.bound, "plain")
+
+
+def test_synchronous_rounds_helper(oracle_mod):
+    """The numpy synchronous-rounds iteration used by the device tests reaches
+    the oracle's least fixpoint, and its first round lifts exactly L_1."""
+    for game in (synth.gen_plain(), synth.gen_uniform(700, 3, 5, 13), synth.gen_rmat(8, 8, seed=3)):
+        want = oracle_mod.solve(game)
+        f, rounds, lifts, changes, edges = pins.synchronous_rounds_numpy(game, want.bound)
+        pins.expect_equal(f, want.f, game.name)
+        assert rounds >= 1 and lifts >= changes >= 1
+        assert lifts >= int(pins.initially_active_numpy(game).sum())
