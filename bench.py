@@ -25,7 +25,8 @@ Flags: --gpus N (only 1 is supported: the solver runs on one GPU),
 --steps K, --warmup W, --config {uniform,plain,rmat,torus}, --no-cpu-baseline,
 --sweep R (instead of solves: R full-frontier lift rounds, every vertex active),
 --max-rounds M (profiling only: stops each solve after M rounds; the line is
-then marked partial), --serve-games G (0 = no serving report).
+then marked partial), --serve-games G (0 = no serving report), --shape k=v,...
+(launch-shape fields overriding the tuned ones).
 """
 from __future__ import annotations
 
@@ -161,6 +162,7 @@ def main():
     ap.add_argument("--sweep", type=int, default=0)
     ap.add_argument("--max-rounds", type=int, default=0)
     ap.add_argument("--serve-games", type=int, default=32)
+    ap.add_argument("--shape", default="", help="launch-shape overrides, e.g. partition=1,blocks_per_cu=4")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported; the solver runs on one GPU "
@@ -182,6 +184,11 @@ def main():
     from paper_1710_03647_amd import tune
 
     shape = tune.config_for(game)
+    for kv in filter(None, args.shape.split(",")):
+        k, v = kv.split("=")
+        if k not in tune.DEFAULTS:
+            raise SystemExit(f"unknown launch-shape field {k}")
+        shape[k] = int(v)
     log(f"[bench] launch shape: {shape}")
     ctx = eg.Context(0, stream=stream, **shape)
     # kernels loaded once, untimed (a small game)

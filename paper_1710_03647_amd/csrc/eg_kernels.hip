@@ -381,6 +381,60 @@ __device__ __forceinline__ void activate(const DevGame& g, RoundShared<V>& sh, b
   }
 }
 
+// Edges [x0, x0 + J * BLOCK) of the tile's flattened edge range (lanes past E
+// re-read the last edge and contribute nothing).  Every lane issues its J edge
+// loads and then its J gathers of f with no branch in between, so the gathers
+// of a lane overlap instead of each waiting for the one before.
+template <typename V, int J>
+__device__ __forceinline__ void lift_edges(const DevGame& g, RoundShared<V>& sh, const V* f, uint32_t x0,
+                                           uint32_t E) {
+  const uint32_t tid = threadIdx.x;
+  uint32_t slot[J];
+  bool neg[J];
+  int2 ed[J];
+#pragma unroll
+  for (int j = 0; j < J; j++) {
+    const uint32_t x = x0 + j * BLOCK + tid;
+    const uint32_t xc = x < E ? x : E - 1;
+    const uint32_t s = find_range(sh.epre, xc);
+    const uint32_t beg = sh.ebeg[s];
+    slot[j] = x < E ? s : (uint32_t)BLOCK;
+    neg[j] = (beg & OWNER_BIT) != 0;
+    ed[j] = load_edge(g.edges, (beg & ROW_MASK) + (xc - sh.epre[s]));
+  }
+  V fu[J];
+#pragma unroll
+  for (int j = 0; j < J; j++) fu[j] = f[ed[j].x];
+#pragma unroll
+  for (int j = 0; j < J; j++) {
+    V tm = fu[j] - (V)ed[j].y;
+    tm = tm > V(0) ? tm : V(0);
+    if (slot[j] < BLOCK)
+      __hip_atomic_fetch_min(&sh.key[slot[j]], neg[j] ? -tm : tm, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+}
+
+// Predecessor entries [x0, x0 + J * BLOCK) of the tile's changed vertices,
+// loaded the same way, then activated for the next round.
+template <bool DENSE, typename V, int J>
+__device__ __forceinline__ void scan_preds(const DevGame& g, RoundShared<V>& sh, uint32_t x0, uint32_t P,
+                                           uint8_t* act_next, int32_t* wl_out, uint32_t* cnt_out,
+                                           unsigned long long& pushes) {
+  const uint32_t tid = threadIdx.x;
+  int32_t pr[J];
+#pragma unroll
+  for (int j = 0; j < J; j++) {
+    const uint32_t x = x0 + j * BLOCK + tid;
+    const uint32_t xc = x < P ? x : P - 1;
+    const uint32_t s = find_range(sh.ppre, xc);
+    pr[j] = load_stream(g.rev_src + sh.pbeg[s] + (xc - sh.ppre[s]));
+    if (x >= P) pr[j] = -1;
+  }
+#pragma unroll
+  for (int j = 0; j < J; j++) activate<DENSE>(g, sh, pr[j] >= 0, pr[j], act_next, wl_out, cnt_out, pushes);
+}
+
+
 // Build L_1: f = 0 (kept on resume) and the round-1 flag on the initially active
 // vertices, whose flags were derived from the weights when the game was
 // created (player 0: every out-edge negative; player 1: some out-edge
@@ -497,32 +551,19 @@ __device__ __forceinline__ void round_tile(const DevGame& g, RoundShared<V>& sh,
   block_sync();
   if (E == 0) return;  // block-uniform: no active vertex in this tile
 
-  for (uint32_t x0 = 0; x0 < (PART ? 0u : E); x0 += BLOCK * UNROLL) {
-    uint32_t slot[UNROLL];
-    int2 ed[UNROLL];
-    V fu[UNROLL];
-#pragma unroll
-    for (int j = 0; j < UNROLL; j++) {
-      const uint32_t x = x0 + j * BLOCK + tid;
-      slot[j] = BLOCK;
-      if (x < E) {
-        const uint32_t s = find_range(sh.epre, x);
-        slot[j] = s;
-        ed[j] = load_edge(g.edges, (sh.ebeg[s] & ROW_MASK) + (x - sh.epre[s]));
+  if (!PART)
+    for (uint32_t x0 = 0; x0 < E; x0 += BLOCK * UNROLL) {
+      switch (std::min<uint32_t>((E - x0 + BLOCK - 1) / BLOCK, UNROLL)) {
+        case 1: lift_edges<V, 1>(g, sh, f, x0, E); break;
+        case 2: lift_edges<V, 2>(g, sh, f, x0, E); break;
+        case 3: lift_edges<V, 3>(g, sh, f, x0, E); break;
+        case 4: lift_edges<V, 4>(g, sh, f, x0, E); break;
+        case 5: lift_edges<V, 5>(g, sh, f, x0, E); break;
+        case 6: lift_edges<V, 6>(g, sh, f, x0, E); break;
+        case 7: lift_edges<V, 7>(g, sh, f, x0, E); break;
+        default: lift_edges<V, UNROLL>(g, sh, f, x0, E); break;
       }
     }
-#pragma unroll
-    for (int j = 0; j < UNROLL; j++)
-      if (slot[j] < BLOCK) fu[j] = f[ed[j].x];
-#pragma unroll
-    for (int j = 0; j < UNROLL; j++)
-      if (slot[j] < BLOCK) {
-        V tm = fu[j] - (V)ed[j].y;
-        tm = tm > V(0) ? tm : V(0);
-        __hip_atomic_fetch_min(&sh.key[slot[j]], (sh.ebeg[slot[j]] & OWNER_BIT) ? -tm : tm,
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-      }
-  }
   block_sync();
 
   uint32_t ideg = 0;
@@ -530,6 +571,11 @@ __device__ __forceinline__ void round_tile(const DevGame& g, RoundShared<V>& sh,
     const V k = sh.key[tid];
     V nv = (raw & OWNER_BIT) ? -k : k;
     if (nv > bound) nv = top;
+    // Writes never lower a value.  From f = 0 (or any measure below the least
+    // fixpoint that lifts do not lower) this changes nothing; from a measure
+    // with values raised by other means it keeps every stop point a
+    // pre-fixpoint, and the least pre-fixpoint is the least fixpoint.
+    if (nv < old) nv = old;
     c.lifts++;
     c.edges += deg;
     if (nv != old) {
@@ -546,18 +592,42 @@ __device__ __forceinline__ void round_tile(const DevGame& g, RoundShared<V>& sh,
   c.scanned += ideg;
   block_sync();
   for (uint32_t x0 = 0; x0 < P; x0 += BLOCK * UNROLL) {
-    int32_t pr[UNROLL];
-#pragma unroll
-    for (int j = 0; j < UNROLL; j++) {
-      const uint32_t x = x0 + j * BLOCK + tid;
-      pr[j] = -1;
-      if (x < P) {
-        const uint32_t s = find_range(sh.ppre, x);
-        pr[j] = load_stream(g.rev_src + sh.pbeg[s] + (x - sh.ppre[s]));
-      }
+    switch (std::min<uint32_t>((P - x0 + BLOCK - 1) / BLOCK, UNROLL)) {
+      case 1: scan_preds<DENSE, V, 1>(g, sh, x0, P, act_next, wl_out, cnt_out, c.pushes); break;
+      case 2: scan_preds<DENSE, V, 2>(g, sh, x0, P, act_next, wl_out, cnt_out, c.pushes); break;
+      case 3: scan_preds<DENSE, V, 3>(g, sh, x0, P, act_next, wl_out, cnt_out, c.pushes); break;
+      case 4: scan_preds<DENSE, V, 4>(g, sh, x0, P, act_next, wl_out, cnt_out, c.pushes); break;
+      case 5: scan_preds<DENSE, V, 5>(g, sh, x0, P, act_next, wl_out, cnt_out, c.pushes); break;
+      case 6: scan_preds<DENSE, V, 6>(g, sh, x0, P, act_next, wl_out, cnt_out, c.pushes); break;
+      case 7: scan_preds<DENSE, V, 7>(g, sh, x0, P, act_next, wl_out, cnt_out, c.pushes); break;
+      default: scan_preds<DENSE, V, UNROLL>(g, sh, x0, P, act_next, wl_out, cnt_out, c.pushes); break;
     }
+  }
+}
+
+// Records [x0, x0 + J * BLOCK) of a chunk of the target-sliced edge copy into
+// the tile's LDS keys (loads first, as in lift_edges).
+template <typename V, int J>
+__device__ __forceinline__ void slice_edges(const DevGame& g, V* key, const uint32_t* own, const V* f, uint32_t x0,
+                                            uint32_t end) {
+  const uint32_t tid = threadIdx.x;
+  int2 ed[J];
 #pragma unroll
-    for (int j = 0; j < UNROLL; j++) activate<DENSE>(g, sh, pr[j] >= 0, pr[j], act_next, wl_out, cnt_out, c.pushes);
+  for (int j = 0; j < J; j++) {
+    const uint32_t x = x0 + j * BLOCK + tid;
+    ed[j] = g.pedges[x < end ? x : end - 1];
+  }
+  V fu[J];
+#pragma unroll
+  for (int j = 0; j < J; j++) fu[j] = f[(uint32_t)ed[j].x & ((1u << PTILE_SHIFT) - 1)];
+#pragma unroll
+  for (int j = 0; j < J; j++) {
+    const uint32_t loc = (uint32_t)ed[j].x >> PTILE_SHIFT;
+    V tm = fu[j] - (V)ed[j].y;
+    tm = tm > V(0) ? tm : V(0);
+    if (x0 + j * BLOCK + tid < end)
+      __hip_atomic_fetch_min(&key[loc], ((own[loc >> 5] >> (loc & 31)) & 1u) ? -tm : tm, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_WORKGROUP);
   }
 }
 
@@ -592,25 +662,16 @@ __global__ __launch_bounds__(BLOCK) void k_partial(DevGame g, uint32_t r) {
     const uint32_t c = tile * nparts + q;
     const uint32_t beg = g.poff[c], end = g.poff[c + 1];
     for (uint32_t x0 = beg; x0 < end; x0 += BLOCK * UNROLL) {
-      int2 ed[UNROLL];
-      V fu[UNROLL];
-#pragma unroll
-      for (int j = 0; j < UNROLL; j++) {
-        const uint32_t x = x0 + j * BLOCK + tid;
-        if (x < end) ed[j] = g.pedges[x];
+      switch (std::min<uint32_t>((end - x0 + BLOCK - 1) / BLOCK, UNROLL)) {
+        case 1: slice_edges<V, 1>(g, key, own, f, x0, end); break;
+        case 2: slice_edges<V, 2>(g, key, own, f, x0, end); break;
+        case 3: slice_edges<V, 3>(g, key, own, f, x0, end); break;
+        case 4: slice_edges<V, 4>(g, key, own, f, x0, end); break;
+        case 5: slice_edges<V, 5>(g, key, own, f, x0, end); break;
+        case 6: slice_edges<V, 6>(g, key, own, f, x0, end); break;
+        case 7: slice_edges<V, 7>(g, key, own, f, x0, end); break;
+        default: slice_edges<V, UNROLL>(g, key, own, f, x0, end); break;
       }
-#pragma unroll
-      for (int j = 0; j < UNROLL; j++)
-        if (x0 + j * BLOCK + tid < end) fu[j] = f[(uint32_t)ed[j].x & ((1u << PTILE_SHIFT) - 1)];
-#pragma unroll
-      for (int j = 0; j < UNROLL; j++)
-        if (x0 + j * BLOCK + tid < end) {
-          const uint32_t loc = (uint32_t)ed[j].x >> PTILE_SHIFT;
-          V tm = fu[j] - (V)ed[j].y;
-          tm = tm > V(0) ? tm : V(0);
-          __hip_atomic_fetch_min(&key[loc], ((own[loc >> 5] >> (loc & 31)) & 1u) ? -tm : tm, __ATOMIC_RELAXED,
-                                 __HIP_MEMORY_SCOPE_WORKGROUP);
-        }
     }
     block_sync();
     V* part = (V*)g.part + (size_t)q * n;

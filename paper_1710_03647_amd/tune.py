@@ -33,7 +33,7 @@ SPACE = {
     "blocks_per_cu": [4, 8],
     "dense_div": [8, 32],
     "small_limit": [512, 1024, 4096],
-    "partition": [0, 1],
+    "partition": [0, 2],
 }
 
 
