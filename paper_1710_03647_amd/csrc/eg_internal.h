@@ -60,20 +60,26 @@ struct DevGame {
 constexpr uint32_t PTILE = 1024;        // vertices per tile of the partitioned copy
 constexpr uint32_t PTILE_SHIFT = 22;    // tile-local source index sits above the 22 target bits
 
-// Slot states of the batched iteration.
+// Slot states of the batched iteration, and where a running slot's rounds run:
+// in the epochs (flag sweeps, one round per epoch) or in k_batch_small (lists,
+// many rounds per launch; SMALL_NEW until its flags have become a list).
 constexpr uint32_t SLOT_FREE = 0, SLOT_RUN = 1, SLOT_DONE = 2;
+constexpr uint32_t BM_DENSE = 0, BM_SMALL_NEW = 1, BM_SMALL = 2;
 
 // Slot table of the batched iteration (device pointers, passed by value).
 enum BatchCtl : int { B_EPOCH = 0, B_TASKS = 1, B_WORDS = 4 };
 struct BatchTable {
   const DevGame* games;       // nslots descriptors
   uint32_t* state;            // SLOT_FREE / SLOT_RUN / SLOT_DONE
-  uint32_t* join;             // epoch in which the game runs its round 1
-  uint32_t* rounds;           // rounds run, written when the game is retired
+  uint32_t* mode;             // BM_DENSE / BM_SMALL_NEW / BM_SMALL
+  uint32_t* round;            // next round of each running game
+  uint32_t* cur;              // round a slot in the epochs runs in the current epoch
+  uint32_t* rounds;           // rounds run, written when the game finishes
   uint32_t* task_begin;       // nslots + 1: first task of each slot in the current epoch
   unsigned long long* st;     // nslots * S_WORDS counters
   uint32_t* ctl;              // B_WORDS
   uint32_t nslots;
+  uint32_t small_limit;       // lists up to this length run in k_batch_small
 };
 
 // Device layout of one game: every array in one allocation.
@@ -110,6 +116,7 @@ size_t staging_bytes(int32_t n, int64_t m, bool host_inputs);
 hipError_t upload_game(const eg_game_desc* d, const HostPrep& prep, DevGame& dg, void* staging, hipStream_t s,
                        hipEvent_t after_layout);
 hipError_t launch_epoch(const BatchTable& bt, int grid, hipStream_t s);
+hipError_t launch_batch_small(const BatchTable& bt, uint32_t max_rounds, hipStream_t s);
 
 // Layout and predecessor lists (eg_kernels.hip)
 hipError_t launch_layout(const int64_t* off, const uint8_t* owner_bits, const int32_t* tgt,

@@ -735,18 +735,14 @@ __global__ __launch_bounds__(BLOCK) void k_round(DevGame g, uint32_t r) {
 // Many rounds of one game in a single block, for small active sets: a round
 // of a few tiles costs a few dependent cache hits here instead of a kernel
 // launch.  Starts at round r0 (sparse list), stops before a round whose list
-// is empty (the fixpoint) or longer than `limit`, or after `max_rounds`;
-// ctrl[C_NEXT] receives the round to run next.  All waves of the block share
-// one CU and its caches, so the block barrier orders rounds.
+// is empty (the fixpoint) or longer than `limit`, or after `max_rounds`, and
+// returns the round to run next (k_rounds_small stores it in ctrl[C_NEXT]).
+// All waves of the block share one CU and its caches, so the block barrier
+// orders rounds.
 template <typename V>
-__global__ __launch_bounds__(BLOCK) void k_rounds_small(DevGame g, uint32_t r0, uint32_t max_rounds,
-                                                         uint32_t limit) {
-  __shared__ RoundShared<V> sh;
-  __shared__ uint32_t s_items;
-  __shared__ int s_changed;
+__device__ uint32_t small_rounds(const DevGame& g, RoundShared<V>& sh, uint32_t r0, uint32_t max_rounds,
+                                 uint32_t limit, uint32_t& s_items, int& s_changed, Counters& c) {
   const uint32_t tid = threadIdx.x;
-  if (tid < S_WORDS) sh.st[tid] = 0;
-  Counters c;
   uint32_t r = r0;
   for (uint32_t k = 0; k < max_rounds; k++, r++) {
     block_sync();
@@ -781,6 +777,19 @@ __global__ __launch_bounds__(BLOCK) void k_rounds_small(DevGame g, uint32_t r0, 
     if (tid == 0 && s_changed) g.ctrl[C_ANY0 + r % 3] = 1;
   }
   block_sync();
+  return r;
+}
+
+template <typename V>
+__global__ __launch_bounds__(BLOCK) void k_rounds_small(DevGame g, uint32_t r0, uint32_t max_rounds,
+                                                         uint32_t limit) {
+  __shared__ RoundShared<V> sh;
+  __shared__ uint32_t s_items;
+  __shared__ int s_changed;
+  const uint32_t tid = threadIdx.x;
+  if (tid < S_WORDS) sh.st[tid] = 0;
+  Counters c;
+  const uint32_t r = small_rounds<V>(g, sh, r0, max_rounds, limit, s_items, s_changed, c);
   block_counters(sh, c);
   if (tid < S_WORDS) g.slots[tid] += sh.st[tid];
   if (tid == 0) g.ctrl[C_NEXT] = r;
@@ -798,11 +807,12 @@ hipError_t launch_rounds_small(const DevGame& g, int vbits, uint32_t r0, uint32_
 // ---------------------------------------------------------------- batched games
 //
 // Many games share one launch per round.  The slot table holds one DevGame
-// per resident game; game s runs its round r = epoch - join[s] + 1 in epoch
-// `epoch`, independently of the others.  Each epoch is two launches: k_plan
-// (one block) retires the games whose previous round raised nothing and lays
-// out the tasks of the epoch, one per tile of every running game (dense
-// representation); k_batch_round (a fixed grid) takes tasks in turn.
+// per resident game and the round each game runs next, independently of the
+// others.  Each epoch is two launches: k_plan (one block) retires the games
+// whose previous round raised nothing, sends games whose next active set is
+// small to k_batch_small, and lays out the tasks of the epoch, one per tile
+// of every other running game (dense representation); k_batch_round (a fixed
+// grid) takes tasks in turn.
 
 __global__ __launch_bounds__(1024) void k_plan(BatchTable bt) {
   __shared__ uint32_t wsum[1024 / WAVE];
@@ -814,14 +824,22 @@ __global__ __launch_bounds__(1024) void k_plan(BatchTable bt) {
   for (uint32_t base = 0; base < bt.nslots; base += 1024) {
     const uint32_t s = base + tid;
     uint32_t tasks = 0;
-    if (s < bt.nslots && bt.state[s] == SLOT_RUN) {
-      const uint32_t r = epoch - bt.join[s] + 1;
+    if (s < bt.nslots && bt.state[s] == SLOT_RUN &&
+        __hip_atomic_load(&bt.mode[s], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == BM_DENSE) {
+      const uint32_t r = bt.round[s];
       const DevGame& g = bt.games[s];
       if (g.ctrl[C_ANY0 + (r - 1) % 3] == 0) {  // round r-1 raised nothing: L_r is empty
-        bt.state[s] = SLOT_DONE;
         bt.rounds[s] = r - 1;
+        bt.state[s] = SLOT_DONE;
+      } else if (r > 1 && g.ctrl[C_CNT0 + r % 3] <= bt.small_limit) {
+        // at most small_limit predecessor entries were activated for L_r:
+        // the game continues in k_batch_small
+        __hip_atomic_store(&bt.mode[s], BM_SMALL_NEW, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
       } else {
         g.ctrl[C_ANY0 + (r + 1) % 3] = 0;  // written by round r+1
+        g.ctrl[C_CNT0 + (r + 1) % 3] = 0;  // summed by round r: entries activated for L_{r+1}
+        bt.cur[s] = r;
+        bt.round[s] = r + 1;
         tasks = ((uint32_t)g.n + TILE - 1) / TILE;
       }
     }
@@ -864,37 +882,110 @@ __device__ __forceinline__ uint32_t find_slot(const uint32_t* begin, uint32_t ns
 }
 
 template <typename V>
-__device__ __forceinline__ void batch_task(const BatchTable& bt, RoundShared<V>& sh, uint32_t s, uint32_t t,
-                                           uint32_t epoch) {
+__device__ __forceinline__ void batch_task(const BatchTable& bt, RoundShared<V>& sh, uint32_t s, uint32_t t) {
   const DevGame& g = bt.games[s];
-  const uint32_t r = epoch - bt.join[s] + 1;
+  const uint32_t r = bt.cur[s];
   if (threadIdx.x < S_WORDS) sh.st[threadIdx.x] = 0;
   Counters c;
   round_tile<V, true>(g, sh, r, t, (uint32_t)g.n, c);
   block_sync();
   block_counters(sh, c);
   if (threadIdx.x < S_WORDS && sh.st[threadIdx.x]) atomicAdd(&bt.st[s * S_WORDS + threadIdx.x], sh.st[threadIdx.x]);
-  if (threadIdx.x == 0 && sh.st[S_CHANGES]) g.ctrl[C_ANY0 + r % 3] = 1;
+  if (threadIdx.x == 0) {
+    if (sh.st[S_CHANGES]) g.ctrl[C_ANY0 + r % 3] = 1;
+    if (sh.st[S_SCANNED])
+      atomicAdd(&g.ctrl[C_CNT0 + (r + 1) % 3], (uint32_t)std::min<unsigned long long>(sh.st[S_SCANNED], 1u << 30));
+  }
 }
 
 __global__ __launch_bounds__(BLOCK) void k_batch_round(BatchTable bt) {
   __shared__ RoundShared<int64_t> sh;
   const uint32_t ntasks = bt.ctl[B_TASKS];
-  const uint32_t epoch = bt.ctl[B_EPOCH];
   for (uint32_t x = blockIdx.x; x < ntasks; x += gridDim.x) {
     block_sync();
     const uint32_t s = find_slot(bt.task_begin, bt.nslots, x);
     const uint32_t t = x - bt.task_begin[s];
     if (bt.games[s].top <= INT32_MAX)  // 32-bit values (see the value width rule)
-      batch_task<int32_t>(bt, reinterpret_cast<RoundShared<int32_t>&>(sh), s, t, epoch);
+      batch_task<int32_t>(bt, reinterpret_cast<RoundShared<int32_t>&>(sh), s, t);
     else
-      batch_task<int64_t>(bt, sh, s, t, epoch);
+      batch_task<int64_t>(bt, sh, s, t);
+  }
+}
+
+// Games of the batch whose active set is small run here, one block per game
+// and many rounds per launch, on a stream of their own beside the epochs of
+// the others (a slot is either in the epochs or here, by its mode word).
+// A slot that enters from the epochs first turns its round's flags into a
+// list.  Afterwards the slot is finished (empty list), handed back to the
+// epochs (list longer than small_limit) or kept here.
+template <typename V>
+__device__ void batch_small_slot(const BatchTable& bt, RoundShared<V>& sh, uint32_t s, uint32_t mode,
+                                 uint32_t max_rounds, uint32_t& s_items, int& s_changed) {
+  const DevGame& g = bt.games[s];
+  const uint32_t tid = threadIdx.x;
+  const uint32_t n = (uint32_t)g.n;
+  uint32_t r = bt.round[s];
+  if (mode == BM_SMALL_NEW) {
+    if (tid == 0) s_items = 0;
+    block_sync();
+    const uint8_t* act = (r & 1) ? g.act1 : g.act0;
+    int32_t* wl = (r & 1) ? g.wl1 : g.wl0;
+    for (uint32_t v0 = 0; v0 < n; v0 += BLOCK) {
+      const uint32_t v = v0 + tid;
+      wave_append(v < n && act[v] != 0, (int32_t)v, wl, &s_items);
+    }
+    block_sync();
+    if (tid == 0) {
+      g.ctrl[C_CNT0 + r % 3] = s_items;
+      g.ctrl[C_CNT0 + (r + 1) % 3] = 0;
+      g.ctrl[C_CNT0 + (r + 2) % 3] = 0;
+    }
+  }
+  if (tid < S_WORDS) sh.st[tid] = 0;
+  Counters c;
+  r = small_rounds<V>(g, sh, r, max_rounds, bt.small_limit, s_items, s_changed, c);
+  block_counters(sh, c);
+  if (tid < S_WORDS && sh.st[tid]) atomicAdd(&bt.st[s * S_WORDS + tid], sh.st[tid]);
+  if (tid == 0) {
+    const uint32_t items = g.ctrl[C_CNT0 + r % 3];
+    bt.round[s] = r;
+    if (items == 0) bt.rounds[s] = r - 1;
+    __threadfence();
+    if (items == 0)
+      __hip_atomic_store(&bt.state[s], SLOT_DONE, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    else
+      __hip_atomic_store(&bt.mode[s], items > bt.small_limit ? BM_DENSE : BM_SMALL, __ATOMIC_RELEASE,
+                         __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_batch_small(BatchTable bt, uint32_t max_rounds) {
+  __shared__ RoundShared<int64_t> sh;
+  __shared__ uint32_t s_items, s_mode;
+  __shared__ int s_changed;
+  for (uint32_t s = blockIdx.x; s < bt.nslots; s += gridDim.x) {
+    block_sync();
+    if (threadIdx.x == 0)
+      s_mode = bt.state[s] == SLOT_RUN ? __hip_atomic_load(&bt.mode[s], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)
+                                       : (uint32_t)BM_DENSE;
+    block_sync();
+    if (s_mode == BM_DENSE) continue;
+    if (bt.games[s].top <= INT32_MAX)
+      batch_small_slot<int32_t>(bt, reinterpret_cast<RoundShared<int32_t>&>(sh), s, s_mode, max_rounds, s_items,
+                                s_changed);
+    else
+      batch_small_slot<int64_t>(bt, sh, s, s_mode, max_rounds, s_items, s_changed);
   }
 }
 
 hipError_t launch_epoch(const BatchTable& bt, int grid, hipStream_t s) {
   hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, s, bt);
   hipLaunchKernelGGL(k_batch_round, dim3(grid), dim3(BLOCK), 0, s, bt);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_small(const BatchTable& bt, uint32_t max_rounds, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_small, dim3(bt.nslots), dim3(BLOCK), 0, s, bt, max_rounds);
   return hipGetLastError();
 }
 

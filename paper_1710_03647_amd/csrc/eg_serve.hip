@@ -157,8 +157,9 @@ struct Server {
   void* table_mem = nullptr;
   BatchTable bt{};
   DevGame* h_games = nullptr;  // pinned: descriptors to publish
-  uint32_t* h_words = nullptr; // pinned: per slot {state, join} staging, then state readback
+  uint32_t* h_words = nullptr; // pinned: per slot {state, mode, round} staging
   uint32_t* h_state = nullptr; // pinned: readback of state[]
+  uint32_t* h_mode = nullptr;  // pinned: readback of mode[]
   uint32_t* h_rounds = nullptr;
   unsigned long long* h_st = nullptr;
   std::vector<Ticket*> slot_ticket;
@@ -166,6 +167,7 @@ struct Server {
   uint64_t epochs = 0;
   std::map<int, hipGraphExec_t> graphs;
   hipEvent_t ev_upload = nullptr;
+  hipEvent_t ev_main = nullptr, ev_side = nullptr;
 
   bool init_device(std::string* why);
   void release_device();
@@ -191,6 +193,8 @@ bool Server::init_device(std::string* why) {
   if ((e = hipStreamCreateWithFlags(&main, hipStreamNonBlocking))) return bad("stream", e);
   if ((e = hipStreamCreateWithFlags(&side, hipStreamNonBlocking))) return bad("stream", e);
   if ((e = hipEventCreateWithFlags(&ev_upload, hipEventDisableTiming))) return bad("event", e);
+  if ((e = hipEventCreateWithFlags(&ev_main, hipEventDisableTiming))) return bad("event", e);
+  if ((e = hipEventCreateWithFlags(&ev_side, hipEventDisableTiming))) return bad("event", e);
   size_t free_b = 0, total_b = 0;
   if ((e = hipMemGetInfo(&free_b, &total_b))) return bad("hipMemGetInfo", e);
   size_t budget = cfg.hbm_budget_bytes ? cfg.hbm_budget_bytes : free_b / 4;
@@ -200,9 +204,11 @@ bool Server::init_device(std::string* why) {
     return false;
   }
   const size_t ns = (size_t)nslots;
-  const size_t sizes[] = {sizeof(DevGame) * ns, 4 * ns, 4 * ns, 4 * ns, 4 * (ns + 1), 8 * S_WORDS * ns, 4 * B_WORDS};
-  size_t offs[7], total = 0;
-  for (int i = 0; i < 7; i++) {
+  const size_t sizes[] = {sizeof(DevGame) * ns, 4 * ns, 4 * ns, 4 * ns, 4 * ns, 4 * ns, 4 * (ns + 1),
+                          8 * S_WORDS * ns, 4 * B_WORDS};
+  constexpr int NARR = sizeof(sizes) / sizeof(sizes[0]);
+  size_t offs[NARR], total = 0;
+  for (int i = 0; i < NARR; i++) {
     offs[i] = total;
     total += align_up(sizes[i]);
   }
@@ -211,15 +217,20 @@ bool Server::init_device(std::string* why) {
   char* b = (char*)table_mem;
   bt.games = (const DevGame*)(b + offs[0]);
   bt.state = (uint32_t*)(b + offs[1]);
-  bt.join = (uint32_t*)(b + offs[2]);
-  bt.rounds = (uint32_t*)(b + offs[3]);
-  bt.task_begin = (uint32_t*)(b + offs[4]);
-  bt.st = (unsigned long long*)(b + offs[5]);
-  bt.ctl = (uint32_t*)(b + offs[6]);
+  bt.mode = (uint32_t*)(b + offs[2]);
+  bt.round = (uint32_t*)(b + offs[3]);
+  bt.cur = (uint32_t*)(b + offs[4]);
+  bt.rounds = (uint32_t*)(b + offs[5]);
+  bt.task_begin = (uint32_t*)(b + offs[6]);
+  bt.st = (unsigned long long*)(b + offs[7]);
+  bt.ctl = (uint32_t*)(b + offs[8]);
   bt.nslots = (uint32_t)ns;
+  bt.small_limit = cfg.small_limit > 0 ? (uint32_t)cfg.small_limit : SMALL_LIMIT;
   if ((e = hipHostMalloc((void**)&h_games, sizeof(DevGame) * ns, hipHostMallocDefault))) return bad("pinned", e);
-  if ((e = hipHostMalloc((void**)&h_words, 8 * ns, hipHostMallocDefault))) return bad("pinned", e);
+  if ((e = hipHostMalloc((void**)&h_words, 16 * ns, hipHostMallocDefault))) return bad("pinned", e);
   if ((e = hipHostMalloc((void**)&h_state, 4 * ns, hipHostMallocDefault))) return bad("pinned", e);
+  if ((e = hipHostMalloc((void**)&h_mode, 4 * ns, hipHostMallocDefault))) return bad("pinned", e);
+  for (size_t i = 0; i < ns; i++) h_mode[i] = BM_DENSE;
   if ((e = hipHostMalloc((void**)&h_rounds, 4 * ns, hipHostMallocDefault))) return bad("pinned", e);
   if ((e = hipHostMalloc((void**)&h_st, 8 * S_WORDS * ns, hipHostMallocDefault))) return bad("pinned", e);
   slot_ticket.assign(ns, nullptr);
@@ -237,9 +248,12 @@ void Server::release_device() {
   if (h_games) (void)hipHostFree(h_games);
   if (h_words) (void)hipHostFree(h_words);
   if (h_state) (void)hipHostFree(h_state);
+  if (h_mode) (void)hipHostFree(h_mode);
   if (h_rounds) (void)hipHostFree(h_rounds);
   if (h_st) (void)hipHostFree(h_st);
   if (ev_upload) (void)hipEventDestroy(ev_upload);
+  if (ev_main) (void)hipEventDestroy(ev_main);
+  if (ev_side) (void)hipEventDestroy(ev_side);
   if (main) (void)hipStreamDestroy(main);
   if (side) (void)hipStreamDestroy(side);
   table_mem = nullptr;
@@ -288,14 +302,16 @@ int Server::admit_one(Ticket* t) {
   if (!e) e = hipStreamWaitEvent(main, ev_upload, 0);
   if (!e) e = hipMemsetAsync(dg.ctrl, 0, 4 * C_WORDS, main);
   if (!e) e = launch_init(dg, vbits, 0, (int)nblk, main);
-  // publish: descriptor, zero counters, join epoch, state
+  // publish: descriptor, zero counters, mode and first round, then the state
   h_games[slot] = dg;
-  h_words[2 * slot] = SLOT_RUN;
-  h_words[2 * slot + 1] = (uint32_t)(epochs + 1);
+  h_words[4 * slot] = SLOT_RUN;
+  h_words[4 * slot + 1] = BM_DENSE;
+  h_words[4 * slot + 2] = 1;
   if (!e) e = hipMemcpyAsync((void*)(bt.games + slot), &h_games[slot], sizeof(DevGame), hipMemcpyHostToDevice, main);
   if (!e) e = hipMemsetAsync(bt.st + (size_t)slot * S_WORDS, 0, 8 * S_WORDS, main);
-  if (!e) e = hipMemcpyAsync(bt.join + slot, &h_words[2 * slot + 1], 4, hipMemcpyHostToDevice, main);
-  if (!e) e = hipMemcpyAsync(bt.state + slot, &h_words[2 * slot], 4, hipMemcpyHostToDevice, main);
+  if (!e) e = hipMemcpyAsync(bt.mode + slot, &h_words[4 * slot + 1], 4, hipMemcpyHostToDevice, main);
+  if (!e) e = hipMemcpyAsync(bt.round + slot, &h_words[4 * slot + 2], 4, hipMemcpyHostToDevice, main);
+  if (!e) e = hipMemcpyAsync(bt.state + slot, &h_words[4 * slot], 4, hipMemcpyHostToDevice, main);
   // the staging part of the game's range is free once the side stream is done
   if (!e) e = hipStreamSynchronize(side);
   if (e) {
@@ -306,6 +322,7 @@ int Server::admit_one(Ticket* t) {
     return -1;
   }
   slot_ticket[slot] = t;
+  h_mode[slot] = BM_DENSE;
   nrunning++;
   t->t_admit = now_s();
   return 1;
@@ -315,8 +332,8 @@ int Server::admit_one(Ticket* t) {
 void Server::retire(int slot, bool finished) {
   Ticket* t = slot_ticket[slot];
   hipError_t e = hipSuccess;
-  h_words[2 * slot] = SLOT_FREE;
-  e = hipMemcpyAsync(bt.state + slot, &h_words[2 * slot], 4, hipMemcpyHostToDevice, main);
+  h_words[4 * slot] = SLOT_FREE;
+  e = hipMemcpyAsync(bt.state + slot, &h_words[4 * slot], 4, hipMemcpyHostToDevice, main);
   if (finished) {
     t->credits.resize((size_t)t->n);
     if (!e) e = launch_output(t->dg, t->dg.vbits, t->out64, main);
@@ -402,11 +419,24 @@ void Server::run() {
       k = 1;
       continue;
     }
-    // k epochs, then look for finished games
-    hipGraphExec_t ex = graph_for(k);
-    hipError_t e = ex ? hipGraphLaunch(ex, main) : hipErrorUnknown;
-    epochs += (uint64_t)k;
+    // k epochs for the games in the epochs and, beside them on the side
+    // stream, many rounds of each game in small mode; then look for finished
+    // games.  Slots change hands only through their mode word, and nothing
+    // is admitted or retired while either stream runs.
+    int in_epochs = 0;
+    for (int sl = 0; sl < nslots; sl++) in_epochs += slot_ticket[sl] && h_mode[sl] == BM_DENSE;
+    hipError_t e = hipEventRecord(ev_main, main);
+    if (!e) e = hipStreamWaitEvent(side, ev_main, 0);
+    if (!e && in_epochs) {
+      hipGraphExec_t ex = graph_for(k);
+      e = ex ? hipGraphLaunch(ex, main) : hipErrorUnknown;
+      epochs += (uint64_t)k;
+    }
+    if (!e) e = launch_batch_small(bt, in_epochs ? 8u * (uint32_t)k : 8192u, side);
+    if (!e) e = hipEventRecord(ev_side, side);
+    if (!e) e = hipStreamWaitEvent(main, ev_side, 0);
     if (!e) e = hipMemcpyAsync(h_state, bt.state, 4 * (size_t)nslots, hipMemcpyDeviceToHost, main);
+    if (!e) e = hipMemcpyAsync(h_mode, bt.mode, 4 * (size_t)nslots, hipMemcpyDeviceToHost, main);
     if (!e) e = hipMemcpyAsync(h_rounds, bt.rounds, 4 * (size_t)nslots, hipMemcpyDeviceToHost, main);
     if (!e) e = hipStreamSynchronize(main);
     if (e) {

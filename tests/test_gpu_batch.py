@@ -108,3 +108,20 @@ def test_many_small_games_one_at_a_time_vs_batched(oracle_mod):
         res = ctx.solve_batch(games)
     for g, (f, st) in zip(games, res):
         pins.expect_equal(f, oracle_mod.solve(g).f, g.name)
+
+
+def test_small_mode_in_the_batch_counts_every_lift(oracle_mod):
+    """Games whose active sets shrink finish in the batch's small mode (one
+    block, many rounds per launch) beside games still in the epochs: CF8's
+    climb keeps its exact lift and change counts, and every game matches the
+    oracle."""
+    climbs = [pins.cf8_game(k) for k in (5, 400, 3000)]
+    others = [synth.gen_torus(24, seed=4), synth.gen_uniform(4000, 8, 100, 7), synth.gen_rmat(11, 16, seed=3)]
+    games = climbs + others
+    with eg.Context(0, hbm_budget_bytes=2 * GiB) as ctx:
+        res = ctx.solve_batch(games)
+    for k, (f, st) in zip((5, 400, 3000), res[:3]):
+        pins.expect_equal(f, [pins.TOP] + [0] * k, f"CF8 k={k}")
+        assert st["changes"] == k + 1 and st["lifts"] == k + 2
+    for g, (f, st) in zip(others, res[3:]):
+        pins.expect_equal(f, oracle_mod.solve(g).f, g.name)
