@@ -75,6 +75,9 @@ typedef struct {
   int blocks_per_cu;         /* resident blocks of 256 threads per compute unit in round kernels: 8 */
   int dense_div;             /* flag sweeps while the active set holds >= n / dense_div vertices: 32 */
   int small_limit;           /* one block runs the rounds while the active set holds <= this: 1024 */
+  int top_seeding;           /* eg_solve: 1 = set TOP on the vertices of negative cycles that player 1
+                                can force (found between rounds, before the first one and at doubling
+                                round counts); exact, the credits do not change, only the work */
 } eg_config;
 
 /* A game in CSR form.  Out-edges of v are e in [offsets[v], offsets[v+1]),
@@ -113,6 +116,8 @@ typedef struct {
   double t_latency;       /* eg_poll: submission to result, seconds */
   uint64_t launched_rounds; /* round kernels launched (empty ones after the fixpoint included) */
   uint64_t dense_rounds;  /* of which in the dense representation */
+  uint64_t seeded;        /* vertices set to TOP by seeding passes (top_seeding) */
+  uint64_t seed_passes;   /* seeding passes run */
 } eg_stats;
 
 /* What eg_check derives from a valid game. */

@@ -154,6 +154,9 @@ struct eg_game {
   uint32_t* h_ctrl = nullptr;
   unsigned long long* h_stats = nullptr;
   hipEvent_t ev[6] = {};
+  void* seed_mem = nullptr;  // TOP-seeding scratch, allocated by the first seeding solve
+  eg::SeedBuf sb{};
+  uint32_t* h_seed = nullptr;
 };
 
 // The exported functions keep the C linkage of their declarations in eg.h.
@@ -197,7 +200,7 @@ int eg_ctx_create(const eg_config* cfg, eg_ctx** out) {
     ctx->own_stream = true;
   }
   if (c.blocks_per_cu < 0 || c.blocks_per_cu > 32 || c.dense_div < 0 || c.small_limit < 0 || c.small_limit > 65536 ||
-      c.partition < 0 || c.partition > 2) {
+      c.partition < 0 || c.partition > 2 || c.top_seeding < 0 || c.top_seeding > 1) {
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
     return fail(EG_EINVAL, "launch-shape field out of range");
@@ -225,6 +228,8 @@ static void game_free(eg_game* g) {
   if (g->h_ctrl) (void)hipHostFree(g->h_ctrl);
   if (g->h_blk) (void)hipHostFree(g->h_blk);
   if (g->h_stats) (void)hipHostFree(g->h_stats);
+  if (g->seed_mem) (void)hipFree(g->seed_mem);
+  if (g->h_seed) (void)hipHostFree(g->h_seed);
   for (auto& e : g->ev)
     if (e) (void)hipEventDestroy(e);
   delete g;
@@ -522,7 +527,27 @@ int eg_solve_ex(eg_game* g, const eg_solve_opts* opts, int64_t* credits, eg_stat
   uint32_t batch = 2;
   double t_kernels = 0;  // device time of the round kernels (back to back within a batch)
   uint64_t dense_rounds = 0;
+  const bool seeding = ctx->cfg.top_seeding != 0;
+  if (seeding && !g->seed_mem) {
+    HIPCHK(hipMalloc(&g->seed_mem, eg::seed_bytes(g->n)));
+    HIPCHK(hipHostMalloc((void**)&g->h_seed, 4, hipHostMallocDefault));
+    eg::bind_seed(g->sb, g->seed_mem, g->n);
+  }
+  uint64_t next_seed = 0, seeded = 0, seed_passes = 0;  // passes before the first round, then at doubling round counts
   while (active) {
+    if (seeding && launched >= next_seed) {
+      HIPCHK(eg::launch_seed(dg, g->vbits, g->sb, r, s));
+      HIPCHK(hipMemcpyAsync(g->h_seed, g->sb.count, 4, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      seed_passes++;
+      next_seed = std::max<uint64_t>(64, 2 * launched);
+      if (*g->h_seed) {
+        // the predecessors of the new TOP vertices are flagged for round r
+        seeded += *g->h_seed;
+        mode = DENSE;
+        batch = 2;
+      }
+    }
     uint64_t allowed = 64;
     if (mode == SMALL) allowed = 8192;
     else allowed = batch;
@@ -616,6 +641,8 @@ int eg_solve_ex(eg_game* g, const eg_solve_opts* opts, int64_t* credits, eg_stat
     st->achieved_gbps = st->t_solve > 0 ? st->model_bytes / st->t_solve / 1e9 : 0;
     st->t_round_kernels = t_kernels;
     st->launched_rounds = launched;
+    st->seeded = seeded;
+    st->seed_passes = seed_passes;
     st->dense_rounds = dense_rounds;
   }
   if (status != EG_OK) return fail(status, "budget exhausted after %llu rounds", (unsigned long long)launched);

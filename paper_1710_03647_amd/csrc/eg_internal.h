@@ -60,6 +60,21 @@ struct DevGame {
 constexpr uint32_t PTILE = 1024;        // vertices per tile of the partitioned copy
 constexpr uint32_t PTILE_SHIFT = 22;    // tile-local source index sits above the 22 target bits
 
+// Scratch of one TOP-seeding pass (device arrays of n entries unless noted).
+struct SeedBuf {
+  int32_t* succ;      // chosen successor in the forced subgraph, -1 if none
+  int32_t* wgt;       // weight of that edge
+  int32_t* p[2];      // pointer-doubling successors (double buffered)
+  int32_t* lo[2];     // smallest vertex id on the walk so far (double buffered)
+  uint8_t* forced;    // 1 for player-1 vertices and for player-0 vertices of out-degree 1
+  uint8_t* oncyc;     // 1 for vertices on a cycle of the chosen edges
+  long long* sum;     // per cycle (indexed by its smallest vertex): total weight
+  uint32_t* count;    // 1 word: vertices newly set to TOP
+};
+size_t seed_bytes(int32_t n);
+void bind_seed(SeedBuf& sb, void* base, int32_t n);
+hipError_t launch_seed(const DevGame& g, int vbits, const SeedBuf& sb, uint32_t r, hipStream_t s);
+
 // Slot states of the batched iteration, and where a running slot's rounds run:
 // in the epochs (flag sweeps, one round per epoch) or in k_batch_small (lists,
 // many rounds per launch; SMALL_NEW until its flags have become a list).

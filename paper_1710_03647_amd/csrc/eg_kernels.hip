@@ -804,6 +804,143 @@ hipError_t launch_rounds_small(const DevGame& g, int vbits, uint32_t r0, uint32_
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- TOP seeding
+//
+// A vertex is TOP exactly when player 1 wins from it.  A cheap proof: fix for
+// every player-1 vertex one out-edge (sigma1), and take the forced subgraph of
+// player-1 vertices and player-0 vertices of out-degree 1.  A cycle of the
+// chosen edges whose weights sum below zero can be forced by player 1 forever
+// (every player-0 vertex on it has no other edge), so by Lemma 1 all its
+// vertices are TOP.  sigma1(v) is the out-edge into the forced subgraph with
+// the largest term under the current measure (the lowest index on ties): the
+// edge a player-1 lift would follow.  The chosen edges form a functional
+// graph; after ceil(log2 n) + 1 doublings succ^(2^k)(v) lies on the cycle that
+// v's walk ends in, the image of that map is exactly the set of cycle
+// vertices, and the smallest vertex id along 2^k >= n steps names the cycle.
+// Setting TOP on those vertices keeps the measure below the least fixpoint,
+// and with writes that never lower a value the iteration still ends at it.
+
+__global__ void k_seed_forced(DevGame g, SeedBuf sb) {
+  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < (uint32_t)g.n; v += gridDim.x * blockDim.x) {
+    const uint32_t a = g.rs[v], b = g.rs[v + 1] & ROW_MASK;
+    sb.forced[v] = (a & OWNER_BIT) || b - (a & ROW_MASK) == 1 ? 1 : 0;
+  }
+}
+
+template <typename V>
+__global__ void k_seed_choose(DevGame g, SeedBuf sb) {
+  const V* f = (const V*)g.f;
+  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < (uint32_t)g.n; v += gridDim.x * blockDim.x) {
+    const uint32_t a = g.rs[v], e0 = a & ROW_MASK, e1 = g.rs[v + 1] & ROW_MASK;
+    int32_t best = -1, bw = 0;
+    if (a & OWNER_BIT) {
+      V bt = -1;
+      for (uint32_t e = e0; e < e1; e++) {
+        const int2 ed = g.edges[e];
+        if (!sb.forced[ed.x]) continue;
+        V tm = f[ed.x] - (V)ed.y;
+        tm = tm > V(0) ? tm : V(0);
+        if (tm > bt) {
+          bt = tm;
+          best = ed.x;
+          bw = ed.y;
+        }
+      }
+    } else if (e1 - e0 == 1) {
+      const int2 ed = g.edges[e0];
+      best = ed.x;
+      bw = ed.y;
+    }
+    sb.succ[v] = best;
+    sb.wgt[v] = bw;
+    sb.p[0][v] = best;
+    sb.lo[0][v] = (int32_t)v;
+    sb.oncyc[v] = 0;
+    sb.sum[v] = 0;
+  }
+}
+
+__global__ void k_seed_jump(int32_t n, const int32_t* p, const int32_t* lo, int32_t* p2, int32_t* lo2) {
+  for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+    const int32_t u = p[v];
+    p2[v] = u >= 0 ? p[u] : -1;
+    lo2[v] = u >= 0 ? min(lo[v], lo[u]) : lo[v];
+  }
+}
+
+__global__ void k_seed_mark(int32_t n, const int32_t* p, uint8_t* oncyc) {
+  for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+    if (p[v] >= 0) oncyc[p[v]] = 1;
+}
+
+__global__ void k_seed_sum(int32_t n, const SeedBuf sb, const int32_t* lo) {
+  for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+    if (sb.oncyc[v]) atomicAdd((unsigned long long*)&sb.sum[lo[v]], (unsigned long long)(long long)sb.wgt[v]);
+}
+
+// TOP on the vertices of negative cycles; their predecessors join L_r (flags).
+template <typename V>
+__global__ void k_seed_apply(DevGame g, const SeedBuf sb, const int32_t* lo, uint32_t r) {
+  V* f = (V*)g.f;
+  const V top = (V)g.top;
+  uint8_t* act = (r & 1) ? g.act1 : g.act0;
+  uint32_t mine = 0;
+  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < (uint32_t)g.n; v += gridDim.x * blockDim.x) {
+    if (!sb.oncyc[v] || sb.sum[lo[v]] >= 0 || f[v] == top) continue;
+    f[v] = top;
+    mine++;
+    for (uint32_t k = g.rev_off[v]; k < g.rev_off[v + 1]; k++) act[g.rev_src[k]] = 1;
+  }
+  if (mine) atomicAdd(sb.count, mine);
+}
+
+size_t seed_bytes(int32_t n) {
+  const size_t nn = (size_t)n;
+  auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  return 6 * up(4 * nn) + 2 * up(nn) + up(8 * nn) + up(4);
+}
+
+void bind_seed(SeedBuf& sb, void* base, int32_t n) {
+  const size_t nn = (size_t)n;
+  auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  char* b = (char*)base;
+  int32_t** a4[6] = {&sb.succ, &sb.wgt, &sb.p[0], &sb.p[1], &sb.lo[0], &sb.lo[1]};
+  for (auto q : a4) {
+    *q = (int32_t*)b;
+    b += up(4 * nn);
+  }
+  sb.forced = (uint8_t*)b;
+  b += up(nn);
+  sb.oncyc = (uint8_t*)b;
+  b += up(nn);
+  sb.sum = (long long*)b;
+  b += up(8 * nn);
+  sb.count = (uint32_t*)b;
+}
+
+// One seeding pass before round r; sb.count receives the number of vertices
+// set to TOP.  When it is nonzero the caller runs round r as a dense round
+// (ctrl[C_ANY0 + (r - 1) % 3] is set here).
+hipError_t launch_seed(const DevGame& g, int vbits, const SeedBuf& sb, uint32_t r, hipStream_t s) {
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(((int64_t)g.n + BLOCK - 1) / BLOCK, 8192));
+  hipError_t e = hipMemsetAsync(sb.count, 0, 4, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_seed_forced, dim3(grid), dim3(BLOCK), 0, s, g, sb);
+  if (vbits == 32) hipLaunchKernelGGL(k_seed_choose<int32_t>, dim3(grid), dim3(BLOCK), 0, s, g, sb);
+  else hipLaunchKernelGGL(k_seed_choose<int64_t>, dim3(grid), dim3(BLOCK), 0, s, g, sb);
+  int cur = 0;
+  for (int64_t span = 1; span <= 2 * (int64_t)g.n; span *= 2, cur ^= 1)
+    hipLaunchKernelGGL(k_seed_jump, dim3(grid), dim3(BLOCK), 0, s, g.n, sb.p[cur], sb.lo[cur], sb.p[cur ^ 1],
+                       sb.lo[cur ^ 1]);
+  hipLaunchKernelGGL(k_seed_mark, dim3(grid), dim3(BLOCK), 0, s, g.n, sb.p[cur], sb.oncyc);
+  hipLaunchKernelGGL(k_seed_sum, dim3(grid), dim3(BLOCK), 0, s, g.n, sb, sb.lo[cur]);
+  if (vbits == 32) hipLaunchKernelGGL(k_seed_apply<int32_t>, dim3(grid), dim3(BLOCK), 0, s, g, sb, sb.lo[cur], r);
+  else hipLaunchKernelGGL(k_seed_apply<int64_t>, dim3(grid), dim3(BLOCK), 0, s, g, sb, sb.lo[cur], r);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return hipMemsetAsync(g.ctrl + C_ANY0 + (r + 2) % 3, 0xFF, 1, s);
+}
+
 // ---------------------------------------------------------------- batched games
 //
 // Many games share one launch per round.  The slot table holds one DevGame

@@ -1,0 +1,80 @@
+"""TOP seeding (negative cycles that player 1 can force, set to TOP between
+rounds) changes the work, never the credits: every game below is checked
+against the oracle with seeding on."""
+import numpy as np
+import pytest
+
+import pins
+from paper_1710_03647_amd import eg, synth
+
+pytestmark = pytest.mark.gpu
+TOP = pins.TOP
+
+
+@pytest.fixture(scope="module")
+def sctx():
+    c = eg.Context(0, top_seeding=1)
+    yield c
+    c.close()
+
+
+def seeded_solve(ctx, game, **kw):
+    with ctx.create(game) as g:
+        f, st, rc = g.solve(**kw)
+    return f, st
+
+
+def test_seeded_brute_force(sctx):
+    pins.pin_brute(lambda g: seeded_solve(sctx, g)[0], count=300, seed0=81_000)
+
+
+@pytest.mark.parametrize("pin", pins.CLOSED_FORMS, ids=lambda p: p.__name__)
+def test_seeded_closed_forms(sctx, pin):
+    pin(lambda g: seeded_solve(sctx, g)[0])
+
+
+SEEDED = [
+    ("plain", synth.gen_plain),
+    ("uniform-4k", lambda: synth.gen_uniform(1 << 12, 16, 1000, 2)),
+    ("uniform-ragged", lambda: synth.gen_uniform(12345, 5, 300, 21)),
+    ("uniform-3000-d4", lambda: synth.gen_uniform(3000, 4, 30, 9)),
+    ("rmat-12", lambda: synth.gen_rmat(12, 16, seed=3)),
+    ("rmat-14", lambda: synth.gen_rmat(14, 16, seed=3)),
+    ("rmat-16-int64", lambda: synth.gen_rmat(16, 16, wlim=40000, seed=5)),
+    ("torus-48", lambda: synth.gen_torus(48, seed=4)),
+]
+
+
+@pytest.mark.parametrize("name,make", SEEDED, ids=[s[0] for s in SEEDED])
+def test_seeded_matches_oracle(sctx, oracle_mod, name, make):
+    game = make()
+    f, st = seeded_solve(sctx, game)
+    pins.expect_equal(f, oracle_mod.solve(game).f, name)
+    assert st["seed_passes"] >= 1
+
+
+def test_seeding_cuts_rounds(sctx, oracle_mod):
+    """A game whose TOP vertices must otherwise climb to the bound: seeding
+    proves them TOP early, so the solve needs far fewer rounds."""
+    game = synth.gen_rmat(14, 16, seed=3)
+    want = oracle_mod.solve(game).f
+    with eg.Context(0) as plain:
+        f0, st0 = seeded_solve(plain, game)
+    f1, st1 = seeded_solve(sctx, game)
+    pins.expect_equal(f0, want, "plain")
+    pins.expect_equal(f1, want, "seeded")
+    assert st1["seeded"] > 0
+    assert st1["rounds"] * 4 < st0["rounds"]
+
+
+def test_seeded_resume_and_repeat(sctx, oracle_mod):
+    game = synth.gen_torus(32, seed=4)
+    want = oracle_mod.solve(game).f
+    noise = synth.to_int(synth.draws(5, 2, 0, game.n), 0, 40)
+    with sctx.create(game) as g:
+        for _ in range(3):
+            f, _, _ = g.solve()
+            pins.expect_equal(f, want, "repeat")
+        g.set_measure(np.minimum(want, noise))
+        f, _, _ = g.solve(resume=True)
+        pins.expect_equal(f, want, "resume")
