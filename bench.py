@@ -15,6 +15,12 @@ Also reported:
                 counter summaries when they match the current kernel source;
   cpu_baseline  the CPU oracle (sequential FIFO worklist, one core) on a
                 bounded sample of the same game: its first lifts, ~15 s of work;
+  seeded        the same game solved with TOP seeding (exact; changes the
+                work, so it is reported apart from `value`), and whether its
+                credits equal the plain solve's;
+  rmat_lift     full-frontier lift rounds of the R-MAT scale-22 game (every
+                vertex active): round-kernel time and algorithmic bytes
+                against the 8 TB/s HBM peak, unsliced and target-sliced;
   serving       the first --serve-games games of the serving stream (n
                 log-uniform in [1e3, 1e5], out-degree U{2..16}, W log-uniform in
                 [10, 1000]): one-game-at-a-time solves, the batched server's
@@ -26,7 +32,8 @@ Flags: --gpus N (only 1 is supported: the solver runs on one GPU),
 --sweep R (instead of solves: R full-frontier lift rounds, every vertex active),
 --max-rounds M (profiling only: stops each solve after M rounds; the line is
 then marked partial), --serve-games G (0 = no serving report), --shape k=v,...
-(launch-shape fields overriding the tuned ones).
+(launch-shape fields overriding the tuned ones), --no-seeded, --no-rmat-lift,
+--rmat-sweeps R (full-frontier rounds timed per R-MAT variant).
 """
 from __future__ import annotations
 
@@ -151,6 +158,55 @@ def serving_report(eg, synth, count):
     return res
 
 
+def seeded_leg(eg, game, stream, shape, plain_out):
+    """The same game solved with TOP seeding (exact: the credits must equal the
+    plain solve's bit for bit); reported beside the plain path because it
+    changes the work."""
+    import numpy as np
+
+    with eg.Context(0, stream=stream, top_seeding=1, **shape) as ctx:
+        with ctx.create(game) as g:
+            g.solve()  # warm
+            f, st, rc = g.solve()
+    same = bool(np.array_equal(f, plain_out))
+    log(f"[bench] seeded: t_solve {st['t_solve'] * 1e3:.2f} ms, rounds {st['rounds']}, seeded {st['seeded']}, "
+        f"identical to the plain solve: {same}")
+    return {"t_solve_s": st["t_solve"], "rounds": st["rounds"], "relaxed_edges": st["relaxed_edges"],
+            "gteps": st["relaxed_edges"] / st["t_solve"] / 1e9 if st["t_solve"] else None,
+            "seeded_vertices": st["seeded"], "seed_passes": st["seed_passes"], "identical_to_plain": same}
+
+
+def rmat_lift_leg(eg, stream, sweeps):
+    """Full-frontier lift rounds of the R-MAT scale-22 game (every vertex
+    active): the round kernel alone, against the HBM roofline."""
+    from paper_1710_03647_amd import synth, tune
+
+    t0 = time.perf_counter()
+    game = synth.gen_rmat_full()
+    log(f"[bench] rmat lift: generated R-MAT 22 in {time.perf_counter() - t0:.1f} s")
+    res = {"workload": "R-MAT scale 22, edge factor 16, full-frontier lift rounds (every vertex active), int64 values",
+           "n": game.n, "m": game.m}
+    base = tune.config_for(game)
+    for label, over in (("unsliced", {}), ("sliced", {"partition": 2})):
+        shape = dict(base, **over)
+        with eg.Context(0, stream=stream, **shape) as ctx:
+            with ctx.create(game) as g:
+                g.solve(max_rounds=1, allow_timeout=True)  # f = 0 plus one round
+                for _ in range(2):
+                    g.solve(max_rounds=1, resume=True, allow_timeout=True)
+                kt = mb = 0.0
+                for _ in range(sweeps):
+                    f, st, rc = g.solve(max_rounds=1, resume=True, allow_timeout=True)
+                    kt += st["t_round_kernels"]
+                    mb += st["model_bytes"]
+        us = kt / sweeps * 1e6
+        gbps = mb / kt / 1e9
+        res[label] = {"us_per_round": us, "model_bytes_per_round": mb / sweeps, "achieved": gbps,
+                      "frac": gbps / HBM_PEAK_GBPS, "shape": shape}
+        log(f"[bench] rmat lift ({label}): {us:.1f} us per round, {gbps:.0f} GB/s = {gbps / HBM_PEAK_GBPS:.3f} of peak")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -163,6 +219,9 @@ def main():
     ap.add_argument("--max-rounds", type=int, default=0)
     ap.add_argument("--serve-games", type=int, default=32)
     ap.add_argument("--shape", default="", help="launch-shape overrides, e.g. partition=1,blocks_per_cu=4")
+    ap.add_argument("--no-seeded", action="store_true")
+    ap.add_argument("--no-rmat-lift", action="store_true")
+    ap.add_argument("--rmat-sweeps", type=int, default=10)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported; the solver runs on one GPU "
@@ -202,6 +261,9 @@ def main():
         f"reverse CSR {g.create_stats['t_rcsr'] * 1e3:.1f} ms)")
     out = np.empty(game.n, dtype=np.int64)
     partial = bool(args.max_rounds)
+
+    if args.sweep:
+        g.solve(out=out, max_rounds=1, allow_timeout=True)  # f = 0 plus one round: a defined measure
 
     def step():
         if args.sweep:
@@ -255,8 +317,12 @@ def main():
     }
     if partial:
         line["partial"] = f"solves stopped after {args.max_rounds} rounds (profiling run)"
+    if not args.sweep and not partial and not args.no_seeded:
+        line["seeded"] = seeded_leg(eg, game, stream, shape, out)
     g.destroy()
     ctx.close()
+    if not args.sweep and not partial and not args.no_rmat_lift:
+        line["rmat_lift"] = rmat_lift_leg(eg, stream, args.rmat_sweeps)
     if args.serve_games and not args.sweep and not partial:
         line["serving"] = serving_report(eg, synth, args.serve_games)
     if not args.no_cpu_baseline:

@@ -20,6 +20,8 @@ from __future__ import annotations
 
 import hashlib
 import math
+import os
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -114,6 +116,19 @@ class Game:
         return np.diff(self.off)
 
 
+def _stable_argsort(keys: np.ndarray) -> np.ndarray:
+    """The stable sort order of ``keys`` (unique, so any stable sort gives it);
+    torch's multithreaded CPU sort when torch is present, numpy's otherwise."""
+    if len(keys) >= 1 << 22:
+        try:
+            import torch
+
+            return torch.sort(torch.from_numpy(np.ascontiguousarray(keys)), stable=True)[1].numpy()
+        except ImportError:
+            pass
+    return np.argsort(keys, kind="stable")
+
+
 def from_edges(n: int, src: np.ndarray, dst: np.ndarray, w: np.ndarray, owner: np.ndarray,
                W: int | None = None, name: str = "", sink_loops: bool = False) -> Game:
     """CSR by a stable counting sort on the source (row order = input order).
@@ -130,7 +145,7 @@ def from_edges(n: int, src: np.ndarray, dst: np.ndarray, w: np.ndarray, owner: n
         src = np.concatenate([src, sinks])
         dst = np.concatenate([dst, sinks])
         w = np.concatenate([w, np.zeros(len(sinks), dtype=np.int64)])
-    order = np.argsort(src, kind="stable")
+    order = _stable_argsort(src)
     deg = np.bincount(src, minlength=n)
     off = np.zeros(n + 1, dtype=np.int64)
     np.cumsum(deg, out=off[1:])
@@ -181,14 +196,25 @@ def gen_rmat(scale: int, edge_factor: int = 16, a: float = 0.57, b: float = 0.19
     src = np.zeros(m0, dtype=np.int64)
     dst = np.zeros(m0, dtype=np.int64)
     ab, abc = a + b, a + b + c
-    eidx = np.arange(m0, dtype=np.uint64)
-    for lvl in range(scale):
-        u = to_unit(draws_at(seed, S_RMAT, eidx * np.uint64(scale) + np.uint64(lvl)))
-        sbit = (u >= ab).astype(np.int64)  # quadrants c, d: source bit 1
-        dbit = (((u >= a) & (u < ab)) | (u >= abc)).astype(np.int64)  # quadrants b, d
-        src = (src << 1) | sbit
-        dst = (dst << 1) | dbit
-        del u, sbit, dbit
+
+    def place(lo: int, hi: int) -> None:
+        # edges [lo, hi): the same draws whatever the chunking
+        eidx = np.arange(lo, hi, dtype=np.uint64)
+        s_, d_ = src[lo:hi], dst[lo:hi]
+        for lvl in range(scale):
+            u = to_unit(draws_at(seed, S_RMAT, eidx * np.uint64(scale) + np.uint64(lvl)))
+            s_ <<= 1
+            s_ |= u >= ab  # quadrants c, d: source bit 1
+            d_ <<= 1
+            d_ |= ((u >= a) & (u < ab)) | (u >= abc)  # quadrants b, d
+
+    chunk = 1 << 20
+    spans = [(lo, min(m0, lo + chunk)) for lo in range(0, m0, chunk)]
+    if len(spans) > 1:
+        with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+            list(ex.map(lambda sp: place(*sp), spans))
+    else:
+        place(0, m0)
     perm = np.argsort(draws(seed, S_PERM, 0, n), kind="stable")  # vertex v -> perm[v]
     src = perm[src]
     dst = perm[dst]
