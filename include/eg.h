@@ -78,6 +78,9 @@ typedef struct {
   int top_seeding;           /* eg_solve: 1 = set TOP on the vertices of negative cycles that player 1
                                 can force (found between rounds, before the first one and at doubling
                                 round counts); exact, the credits do not change, only the work */
+  int seg_edges;             /* launch shape: dense rounds cut a tile of 256 vertices whose out-degrees
+                                sum above this into segments taken by different blocks: 8192
+                                (0 = default, -1 = never cut; else >= 256) */
 } eg_config;
 
 /* A game in CSR form.  Out-edges of v are e in [offsets[v], offsets[v+1]),

@@ -155,6 +155,7 @@ struct eg_game {
   unsigned long long* h_stats = nullptr;
   hipEvent_t ev[6] = {};
   void* seed_mem = nullptr;  // TOP-seeding scratch, allocated by the first seeding solve
+  void* seg_mem = nullptr;   // segment tables and combined keys of edge-balanced dense rounds
   eg::SeedBuf sb{};
   uint32_t* h_seed = nullptr;
 };
@@ -200,7 +201,8 @@ int eg_ctx_create(const eg_config* cfg, eg_ctx** out) {
     ctx->own_stream = true;
   }
   if (c.blocks_per_cu < 0 || c.blocks_per_cu > 32 || c.dense_div < 0 || c.small_limit < 0 || c.small_limit > 65536 ||
-      c.partition < 0 || c.partition > 2 || c.top_seeding < 0 || c.top_seeding > 1) {
+      c.partition < 0 || c.partition > 2 || c.top_seeding < 0 || c.top_seeding > 1 || c.seg_edges < -1 ||
+      (c.seg_edges > 0 && c.seg_edges < 256)) {
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
     return fail(EG_EINVAL, "launch-shape field out of range");
@@ -229,6 +231,7 @@ static void game_free(eg_game* g) {
   if (g->h_blk) (void)hipHostFree(g->h_blk);
   if (g->h_stats) (void)hipHostFree(g->h_stats);
   if (g->seed_mem) (void)hipFree(g->seed_mem);
+  if (g->seg_mem) (void)hipFree(g->seg_mem);
   if (g->h_seed) (void)hipHostFree(g->h_seed);
   for (auto& e : g->ev)
     if (e) (void)hipEventDestroy(e);
@@ -377,7 +380,8 @@ hipError_t upload_game(const eg_game_desc* d, const HostPrep& prep, DevGame& dg,
   return hipSuccess;
 }
 
-int prepare(const eg_game_desc* desc, int bound_mode, hipStream_t s, HostPrep& prep, std::string* why) {
+int prepare(const eg_game_desc* desc, int bound_mode, hipStream_t s, HostPrep& prep, std::string* why,
+            uint32_t seg_edges) {
   HostCopy hc;
   eg_game_desc hd;
   int rc = host_view(desc, s, hc, hd);
@@ -385,7 +389,20 @@ int prepare(const eg_game_desc* desc, int bound_mode, hipStream_t s, HostPrep& p
     *why = t_err;
     return rc;
   }
-  return check_host(&hd, bound_mode, &prep.info, why, &prep.clamp, &prep.act_bits);
+  rc = check_host(&hd, bound_mode, &prep.info, why, &prep.clamp, &prep.act_bits);
+  if (rc != EG_OK) return rc;
+  // segments per tile for edge-balanced dense rounds (full-frontier out-degree sums)
+  if (seg_edges == 0) return EG_OK;
+  const int64_t ntiles = ((int64_t)hd.n + TILE_VERTICES - 1) / TILE_VERTICES;
+  std::vector<uint32_t> nseg((size_t)ntiles);
+  bool cut = false;
+  for (int64_t t = 0; t < ntiles; t++) {
+    const int64_t e = hd.offsets[std::min<int64_t>(hd.n, (t + 1) * TILE_VERTICES)] - hd.offsets[t * TILE_VERTICES];
+    nseg[(size_t)t] = (uint32_t)std::max<int64_t>(1, (e + seg_edges - 1) / seg_edges);
+    cut |= nseg[(size_t)t] > 1;
+  }
+  if (cut) prep.tile_nseg.swap(nseg);
+  return EG_OK;
 }
 
 }  // namespace eg
@@ -397,7 +414,8 @@ int eg_create(eg_ctx* ctx, const eg_game_desc* desc, eg_game** out, eg_stats* st
   hipStream_t s = ctx->stream;
   eg::HostPrep prep;
   std::string why;
-  int rc = eg::prepare(desc, ctx->cfg.bound_mode, s, prep, &why);
+  const uint32_t seg_edges = ctx->cfg.seg_edges < 0 ? 0u : ctx->cfg.seg_edges ? (uint32_t)ctx->cfg.seg_edges : eg::SEG_EDGES;
+  int rc = eg::prepare(desc, ctx->cfg.bound_mode, s, prep, &why, seg_edges);
   if (rc != EG_OK) return fail(rc, "%s", why.c_str());
 
   eg_game* g = new eg_game();
@@ -454,6 +472,42 @@ int eg_create(eg_ctx* ctx, const eg_game_desc* desc, eg_game** out, eg_stats* st
   e = run();
   (void)hipFree(staging);
   if (e != hipSuccess) return cleanup_fail(EG_EDEVICE, "upload/layout/reverse CSR", e);
+  if (!prep.tile_nseg.empty() && dg.nparts == 1) {
+    // edge-balanced dense rounds: one work item per segment of every tile
+    const size_t ntiles = prep.tile_nseg.size();
+    std::vector<uint32_t> item_tile, item_seg;
+    for (size_t t = 0; t < ntiles; t++)
+      for (uint32_t j = 0; j < prep.tile_nseg[t]; j++) {
+        item_tile.push_back((uint32_t)t);
+        item_seg.push_back(j);
+      }
+    const size_t ni = item_tile.size();
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t bytes = 2 * up(4 * ni) + 2 * up(4 * ntiles) + up((size_t)(g->vbits / 8) * nn);
+    if ((e = hipMalloc(&g->seg_mem, bytes)) != hipSuccess) return cleanup_fail(EG_ENOMEM, "segment tables", e);
+    char* b = (char*)g->seg_mem;
+    dg.item_tile = (const uint32_t*)b;
+    b += up(4 * ni);
+    dg.item_seg = (const uint32_t*)b;
+    b += up(4 * ni);
+    dg.tile_nseg = (const uint32_t*)b;
+    b += up(4 * ntiles);
+    dg.tile_done = (uint32_t*)b;
+    b += up(4 * ntiles);
+    dg.gkey = b;
+    dg.nitems = (uint32_t)ni;
+    auto seg_setup = [&]() -> hipError_t {
+      hipError_t r;
+      if ((r = hipMemcpyAsync((void*)dg.item_tile, item_tile.data(), 4 * ni, hipMemcpyHostToDevice, s))) return r;
+      if ((r = hipMemcpyAsync((void*)dg.item_seg, item_seg.data(), 4 * ni, hipMemcpyHostToDevice, s))) return r;
+      if ((r = hipMemcpyAsync((void*)dg.tile_nseg, prep.tile_nseg.data(), 4 * ntiles, hipMemcpyHostToDevice, s)))
+        return r;
+      if ((r = hipMemsetAsync(dg.tile_done, 0, 4 * ntiles, s))) return r;
+      if ((r = eg::launch_gkey_init(dg, g->vbits, s))) return r;
+      return hipStreamSynchronize(s);
+    };
+    if ((e = seg_setup()) != hipSuccess) return cleanup_fail(EG_EDEVICE, "segment tables", e);
+  }
   if (st) {
     memset(st, 0, sizeof *st);
     float ms = 0;
@@ -560,6 +614,8 @@ int eg_solve_ex(eg_game* g, const eg_solve_opts* opts, int64_t* credits, eg_stat
         if (mode == DENSE && dg.nparts > 1) {
           HIPCHK(eg::launch_partial(dg, g->vbits, r, g->part_grid, s));
           HIPCHK(eg::launch_round_parts(dg, g->vbits, r, grid, s));
+        } else if (mode == DENSE && dg.nitems) {
+          HIPCHK(eg::launch_round_seg(dg, g->vbits, r, grid, s));
         } else {
           HIPCHK(eg::launch_round(dg, g->vbits, g->h, mode == DENSE, r, grid, s));
         }

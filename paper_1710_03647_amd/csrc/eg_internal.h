@@ -55,7 +55,17 @@ struct DevGame {
   const uint32_t* poff;     // nchunks + 1: chunk (tile * nparts + slice) starts
   const uint32_t* own_bits; // ceil(n/32): owner bits (1 = player 1)
   void* part;               // nparts * n keys of width vbits (per-slice partial keys)
+  // edge-balanced dense rounds: a tile whose out-degree sum exceeds SEG_EDGES
+  // is cut into segments taken by different blocks (nitems = 0: not used)
+  uint32_t nitems;          // work items of a dense round: one per segment
+  const uint32_t* item_tile; // nitems: tile of the item
+  const uint32_t* item_seg;  // nitems: segment of the tile
+  const uint32_t* tile_nseg; // ntiles: segments of the tile
+  uint32_t* tile_done;      // ntiles: segments of the tile finished in this round
+  void* gkey;               // n keys (width vbits) combined over the segments of cut tiles
 };
+
+constexpr uint32_t SEG_EDGES = 8192;    // out-edges per segment of a cut tile (full frontier)
 
 constexpr uint32_t PTILE = 1024;        // vertices per tile of the partitioned copy
 constexpr uint32_t PTILE_SHIFT = 22;    // tile-local source index sits above the 22 target bits
@@ -121,6 +131,7 @@ struct HostPrep {
   eg_game_info info;
   int64_t clamp;                   // largest stored weight P
   std::vector<uint32_t> act_bits;  // initially active vertices
+  std::vector<uint32_t> tile_nseg; // segments per tile of TILE_VERTICES vertices (empty: no tile is cut)
 };
 int check_host(const eg_game_desc* d, int bound_mode, eg_game_info* info, std::string* why,
                int64_t* clamp_out, std::vector<uint32_t>* act_bits);
@@ -132,6 +143,8 @@ hipError_t upload_game(const eg_game_desc* d, const HostPrep& prep, DevGame& dg,
                        hipEvent_t after_layout);
 hipError_t launch_epoch(const BatchTable& bt, int grid, hipStream_t s);
 hipError_t launch_batch_small(const BatchTable& bt, uint32_t max_rounds, hipStream_t s);
+hipError_t launch_round_seg(const DevGame& g, int vbits, uint32_t r, int grid, hipStream_t s);
+hipError_t launch_gkey_init(const DevGame& g, int vbits, hipStream_t s);
 
 // Layout and predecessor lists (eg_kernels.hip)
 hipError_t launch_layout(const int64_t* off, const uint8_t* owner_bits, const int32_t* tgt,

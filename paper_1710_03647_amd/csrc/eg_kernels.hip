@@ -631,6 +631,155 @@ __device__ __forceinline__ void slice_edges(const DevGame& g, V* key, const uint
   }
 }
 
+// Segment `seg` of `nseg` of a dense tile (full-frontier sizes are balanced:
+// a tile whose out-degree sum exceeds SEG_EDGES is cut so that no block takes
+// much more than SEG_EDGES edges).  Every segment block rebuilds the tile's
+// flattened edge range from the flags, which only the last block clears, and
+// lifts its share of the range into LDS keys.  An uncut tile finishes in its
+// block.  Otherwise each block folds the keys it touched into gkey with
+// atomic min, and the block that finishes the tile's last segment (a counter
+// per tile) completes the round for the whole tile from gkey: the new values,
+// the flag clearing and the predecessor activation.
+template <typename V>
+__device__ __forceinline__ void round_seg(const DevGame& g, RoundShared<V>& sh, uint32_t r, uint32_t t,
+                                          uint32_t seg, uint32_t nseg, Counters& c, uint32_t& s_last) {
+  const uint32_t tid = threadIdx.x;
+  V* f = (V*)g.f;
+  V* gkey = (V*)g.gkey;
+  const V bound = (V)g.bound, top = (V)g.top;
+  uint8_t* act_cur = (r & 1) ? g.act1 : g.act0;
+  uint8_t* act_next = (r & 1) ? g.act0 : g.act1;
+  const uint32_t idx = t * TILE + tid;
+  int32_t v = -1;
+  if (idx < (uint32_t)g.n && act_cur[idx]) v = (int32_t)idx;
+  uint32_t raw = 0, deg = 0, pb = 0, pe = 0;
+  V old = 0;
+  if (v >= 0) {
+    raw = load_stream(g.rs + v);
+    deg = (load_stream(g.rs + v + 1) & ROW_MASK) - (raw & ROW_MASK);
+    old = f[v];
+    pb = load_stream(g.rev_off + v);
+    pe = load_stream(g.rev_off + v + 1);
+  }
+  uint32_t E;
+  const uint32_t ex = block_excl_scan(deg, sh.wsum, &E);
+  sh.epre[tid] = ex;
+  if (tid == BLOCK - 1) sh.epre[BLOCK] = E;
+  sh.ebeg[tid] = raw;
+  const V ident = (raw & OWNER_BIT) ? V(0) : std::numeric_limits<V>::max();
+  sh.key[tid] = ident;
+  block_sync();
+  if (E == 0) return;  // block-uniform, and the same in every segment block of the tile
+  const uint32_t lo = (uint32_t)((uint64_t)E * seg / nseg), hi = (uint32_t)((uint64_t)E * (seg + 1) / nseg);
+  for (uint32_t x0 = lo; x0 < hi; x0 += BLOCK * UNROLL) {
+    switch (std::min<uint32_t>((hi - x0 + BLOCK - 1) / BLOCK, UNROLL)) {
+      case 1: lift_edges<V, 1>(g, sh, f, x0, hi); break;
+      case 2: lift_edges<V, 2>(g, sh, f, x0, hi); break;
+      case 3: lift_edges<V, 3>(g, sh, f, x0, hi); break;
+      case 4: lift_edges<V, 4>(g, sh, f, x0, hi); break;
+      case 5: lift_edges<V, 5>(g, sh, f, x0, hi); break;
+      case 6: lift_edges<V, 6>(g, sh, f, x0, hi); break;
+      case 7: lift_edges<V, 7>(g, sh, f, x0, hi); break;
+      default: lift_edges<V, UNROLL>(g, sh, f, x0, hi); break;
+    }
+  }
+  block_sync();
+  V k = sh.key[tid];
+  if (nseg > 1) {
+    // Keys, tile counter and the last block's reads are device-scope atomics,
+    // performed where every XCD sees them.  Each wave waits until its key
+    // updates are performed before the counter is bumped, so the block that
+    // takes the last segment reads complete keys.  No fence is used: a fence
+    // would write back and invalidate the XCD's L2 and with it the cached f.
+    if (v >= 0 && ex < hi && ex + deg > lo)
+      __hip_atomic_fetch_min(gkey + v, k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_s_waitcnt(0);
+    block_sync();
+    if (tid == 0)
+      s_last = __hip_atomic_fetch_add(&g.tile_done[t], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == nseg - 1
+                   ? 1u
+                   : 0u;
+    block_sync();
+    if (!s_last) return;
+    if (v >= 0) {
+      k = __hip_atomic_load(gkey + v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      gkey[v] = ident;
+    }
+    if (tid == 0) g.tile_done[t] = 0;
+  }
+  uint32_t ideg = 0;
+  if (v >= 0) {
+    act_cur[v] = 0;  // consumed
+    V nv = (raw & OWNER_BIT) ? -k : k;
+    if (nv > bound) nv = top;
+    if (nv < old) nv = old;  // writes never lower a value (see round_tile)
+    c.lifts++;
+    c.edges += deg;
+    if (nv != old) {
+      f[v] = nv;
+      c.changes++;
+      ideg = pe - pb;
+    }
+  }
+  uint32_t P;
+  const uint32_t pex = block_excl_scan(ideg, sh.wsum, &P);
+  sh.ppre[tid] = pex;
+  if (tid == BLOCK - 1) sh.ppre[BLOCK] = P;
+  sh.pbeg[tid] = pb;
+  c.scanned += ideg;
+  block_sync();
+  for (uint32_t x0 = 0; x0 < P; x0 += BLOCK * UNROLL) {
+    switch (std::min<uint32_t>((P - x0 + BLOCK - 1) / BLOCK, UNROLL)) {
+      case 1: scan_preds<true, V, 1>(g, sh, x0, P, act_next, nullptr, nullptr, c.pushes); break;
+      case 2: scan_preds<true, V, 2>(g, sh, x0, P, act_next, nullptr, nullptr, c.pushes); break;
+      case 3: scan_preds<true, V, 3>(g, sh, x0, P, act_next, nullptr, nullptr, c.pushes); break;
+      case 4: scan_preds<true, V, 4>(g, sh, x0, P, act_next, nullptr, nullptr, c.pushes); break;
+      case 5: scan_preds<true, V, 5>(g, sh, x0, P, act_next, nullptr, nullptr, c.pushes); break;
+      case 6: scan_preds<true, V, 6>(g, sh, x0, P, act_next, nullptr, nullptr, c.pushes); break;
+      case 7: scan_preds<true, V, 7>(g, sh, x0, P, act_next, nullptr, nullptr, c.pushes); break;
+      default: scan_preds<true, V, UNROLL>(g, sh, x0, P, act_next, nullptr, nullptr, c.pushes); break;
+    }
+  }
+}
+
+// A dense round over the segments of the tiles (see round_seg).
+template <typename V>
+__global__ __launch_bounds__(BLOCK) void k_round_seg(DevGame g, uint32_t r) {
+  __shared__ RoundShared<V> sh;
+  __shared__ uint32_t s_last;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t items = g.ctrl[C_ANY0 + (r - 1) % 3] ? g.nitems : 0u;
+  if (blockIdx.x == 0 && tid == 0) {
+    g.ctrl[C_CNT0 + (r + 2) % 3] = 0;
+    g.ctrl[C_ANY0 + (r + 1) % 3] = 0;
+    if (items) g.ctrl[C_ROUNDS] += 1;
+  }
+  if (items == 0) {
+    if (tid == 0) g.blk_chg[blockIdx.x] = 0;
+    return;
+  }
+  if (tid < S_WORDS) sh.st[tid] = 0;
+  Counters c;
+  for (uint32_t x = blockIdx.x; x < items; x += gridDim.x) {
+    block_sync();  // the previous item is done with the shared arrays
+    const uint32_t t = g.item_tile[x];
+    round_seg<V>(g, sh, r, t, g.item_seg[x], g.tile_nseg[t], c, s_last);
+  }
+  block_counters(sh, c);
+  if (tid < S_WORDS) g.slots[blockIdx.x * S_WORDS + tid] += sh.st[tid];
+  if (tid == 0) {
+    g.blk_chg[blockIdx.x] = (uint32_t)sh.st[S_CHANGES];
+    if (sh.st[S_CHANGES]) g.ctrl[C_ANY0 + r % 3] = 1;
+  }
+}
+
+template <typename V>
+__global__ void k_gkey_init(DevGame g) {
+  V* gkey = (V*)g.gkey;
+  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < (uint32_t)g.n; v += gridDim.x * blockDim.x)
+    gkey[v] = (g.rs[v] & OWNER_BIT) ? V(0) : std::numeric_limits<V>::max();
+}
+
 // Partial keys of every vertex of a tile over the targets of one slice, for a
 // dense round that reads the partitioned edge copy.  Block b works on the
 // slices of XCD b % 8 (workgroups are dealt to the XCDs in turn), so each
@@ -961,8 +1110,10 @@ __global__ __launch_bounds__(1024) void k_plan(BatchTable bt) {
   for (uint32_t base = 0; base < bt.nslots; base += 1024) {
     const uint32_t s = base + tid;
     uint32_t tasks = 0;
+    // (relaxed: a slot's game data written in k_batch_small is released before
+    // its mode turns dense, and is read by k_batch_round, a later kernel)
     if (s < bt.nslots && bt.state[s] == SLOT_RUN &&
-        __hip_atomic_load(&bt.mode[s], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == BM_DENSE) {
+        __hip_atomic_load(&bt.mode[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == BM_DENSE) {
       const uint32_t r = bt.round[s];
       const DevGame& g = bt.games[s];
       if (g.ctrl[C_ANY0 + (r - 1) % 3] == 0) {  // round r-1 raised nothing: L_r is empty
@@ -1087,7 +1238,6 @@ __device__ void batch_small_slot(const BatchTable& bt, RoundShared<V>& sh, uint3
     const uint32_t items = g.ctrl[C_CNT0 + r % 3];
     bt.round[s] = r;
     if (items == 0) bt.rounds[s] = r - 1;
-    __threadfence();
     if (items == 0)
       __hip_atomic_store(&bt.state[s], SLOT_DONE, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     else
@@ -1102,9 +1252,13 @@ __global__ __launch_bounds__(BLOCK) void k_batch_small(BatchTable bt, uint32_t m
   __shared__ int s_changed;
   for (uint32_t s = blockIdx.x; s < bt.nslots; s += gridDim.x) {
     block_sync();
-    if (threadIdx.x == 0)
-      s_mode = bt.state[s] == SLOT_RUN ? __hip_atomic_load(&bt.mode[s], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)
+    if (threadIdx.x == 0) {
+      s_mode = bt.state[s] == SLOT_RUN ? __hip_atomic_load(&bt.mode[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
                                        : (uint32_t)BM_DENSE;
+      // the slot's game data was released by k_plan or by a previous launch
+      // of this kernel; acquire it only for the slots this block runs
+      if (s_mode != BM_DENSE) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
     block_sync();
     if (s_mode == BM_DENSE) continue;
     if (bt.games[s].top <= INT32_MAX)
@@ -1193,6 +1347,19 @@ hipError_t launch_round(const DevGame& g, int vbits, int h, bool dense, uint32_t
     if (dense) hipLaunchKernelGGL((k_round<int64_t, true>), dim3(grid), dim3(BLOCK), 0, s, g, r);
     else hipLaunchKernelGGL((k_round<int64_t, false>), dim3(grid), dim3(BLOCK), 0, s, g, r);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_round_seg(const DevGame& g, int vbits, uint32_t r, int grid, hipStream_t s) {
+  if (vbits == 32) hipLaunchKernelGGL(k_round_seg<int32_t>, dim3(grid), dim3(BLOCK), 0, s, g, r);
+  else hipLaunchKernelGGL(k_round_seg<int64_t>, dim3(grid), dim3(BLOCK), 0, s, g, r);
+  return hipGetLastError();
+}
+
+hipError_t launch_gkey_init(const DevGame& g, int vbits, hipStream_t s) {
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(((int64_t)g.n + BLOCK - 1) / BLOCK, 8192));
+  if (vbits == 32) hipLaunchKernelGGL(k_gkey_init<int32_t>, dim3(grid), dim3(BLOCK), 0, s, g);
+  else hipLaunchKernelGGL(k_gkey_init<int64_t>, dim3(grid), dim3(BLOCK), 0, s, g);
   return hipGetLastError();
 }
 

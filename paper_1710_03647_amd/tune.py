@@ -1,10 +1,11 @@
 """Autotuner for the launch shape of the round kernels.
 
-The round driver has four knobs (eg_config): resident blocks per compute unit,
+The round driver has five knobs (eg_config): resident blocks per compute unit,
 the active-set size above which rounds sweep flags instead of a list
 (n / dense_div), the size below which one block runs many rounds
-(small_limit), and whether dense rounds read the target-sliced edge copy
-(partition).  Which setting is fastest depends on the graph class: its size,
+(small_limit), whether dense rounds read the target-sliced edge copy
+(partition), and the out-degree sum above which a dense tile is cut into
+segments for several blocks (seg_edges).  Which setting is fastest depends on the graph class: its size,
 its degree and its value width.
 
 `tune(game)` times candidate settings on a proxy of the game's class (the
@@ -28,12 +29,13 @@ import time
 PKG = os.path.dirname(os.path.abspath(__file__))
 TABLE = os.path.join(PKG, "tuning.json")
 
-DEFAULTS = {"blocks_per_cu": 8, "dense_div": 32, "small_limit": 1024, "partition": 0}
+DEFAULTS = {"blocks_per_cu": 8, "dense_div": 32, "small_limit": 1024, "partition": 0, "seg_edges": 0}
 SPACE = {
     "blocks_per_cu": [4, 8],
     "dense_div": [8, 32],
     "small_limit": [512, 1024, 4096],
     "partition": [0, 2],
+    "seg_edges": [0, -1],
 }
 
 

@@ -236,3 +236,30 @@ def test_partitioned_rounds_are_synchronous(oracle_mod, name, make):
     pins.expect_equal(f, want.f, name)
     assert st["dense_rounds"] >= st["rounds"] >= rounds
     assert (st["lifts"], st["changes"], st["relaxed_edges"]) == (lifts, changes, edges)
+
+
+def hub_game(seed=31):
+    """Uniform game plus a few hub vertices with tens of thousands of
+    out-edges, two of them in one tile: dense rounds cut those tiles into
+    segments taken by different blocks."""
+    base = synth.gen_uniform(6000, 4, 50, seed)
+    src = [np.repeat(np.arange(base.n), 4)]
+    dst, w = [base.tgt.astype(np.int64)], [base.w.astype(np.int64)]
+    for hub, k, s in ((7, 30000, 1), (200, 20000, 2), (4100, 9000, 3)):
+        x = synth.draws(seed, 40 + s, 0, 2 * k)
+        src.append(np.full(k, hub))
+        dst.append(synth.to_int(x[:k], 0, base.n - 1))
+        w.append(synth.to_int(x[k:], -50, 50))
+    return synth.from_edges(base.n, np.concatenate(src), np.concatenate(dst), np.concatenate(w), base.owner,
+                            W=50, name="uniform-with-hubs")
+
+
+def test_hub_tiles_are_cut(ctx, oracle_mod):
+    game = hub_game()
+    want = oracle_mod.solve(game).f
+    for _ in range(2):
+        f, st = gpu_solve(ctx, game)
+        pins.expect_equal(f, want, game.name)
+    with eg.Context(0, top_seeding=1) as c:
+        f, st = gpu_solve(c, game)
+    pins.expect_equal(f, want, game.name + " seeded")
