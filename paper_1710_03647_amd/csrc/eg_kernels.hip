@@ -405,12 +405,26 @@ __device__ __forceinline__ void lift_edges(const DevGame& g, RoundShared<V>& sh,
   V fu[J];
 #pragma unroll
   for (int j = 0; j < J; j++) fu[j] = f[ed[j].x];
+  const uint32_t lane = lane_id();
 #pragma unroll
   for (int j = 0; j < J; j++) {
     V tm = fu[j] - (V)ed[j].y;
     tm = tm > V(0) ? tm : V(0);
-    if (slot[j] < BLOCK)
-      __hip_atomic_fetch_min(&sh.key[slot[j]], neg[j] ? -tm : tm, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    // Lanes hold consecutive edges, so lanes of one vertex are contiguous and
+    // its keys are folded across the wave first: one LDS atomic per vertex
+    // and wave instead of one per edge (the edges of a vertex would all hit
+    // the same LDS word).
+    V k = neg[j] ? -tm : tm;
+    const uint32_t sl = slot[j];
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+      const V ko = __shfl_down(k, o, WAVE);
+      const uint32_t so = __shfl_down(sl, o, WAVE);
+      if (lane + o < (uint32_t)WAVE && so == sl) k = ko < k ? ko : k;
+    }
+    const uint32_t sprev = __shfl_up(sl, 1, WAVE);
+    if (sl < BLOCK && (lane == 0 || sprev != sl))
+      __hip_atomic_fetch_min(&sh.key[sl], k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   }
 }
 
