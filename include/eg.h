@@ -81,6 +81,11 @@ typedef struct {
   int seg_edges;             /* launch shape: dense rounds cut a tile of 256 vertices whose out-degrees
                                 sum above this into segments taken by different blocks: 8192
                                 (0 = default, -1 = never cut; else >= 256) */
+  int relabel;               /* eg_create: renumber vertices internally by decreasing in-degree so the
+                                most gathered values share cache lines: 0 = when the largest
+                                in-degree is >= 64x the average (n >= 4096) and dense rounds are
+                                unsliced with tiles cut, 1 = never, 2 = always; credits are always
+                                returned in the caller's numbering */
 } eg_config;
 
 /* A game in CSR form.  Out-edges of v are e in [offsets[v], offsets[v+1]),

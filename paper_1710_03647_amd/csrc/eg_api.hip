@@ -156,6 +156,7 @@ struct eg_game {
   hipEvent_t ev[6] = {};
   void* seed_mem = nullptr;  // TOP-seeding scratch, allocated by the first seeding solve
   void* seg_mem = nullptr;   // segment tables and combined keys of edge-balanced dense rounds
+  void* perm_mem = nullptr;  // internal id of each caller vertex (renumbered games)
   eg::SeedBuf sb{};
   uint32_t* h_seed = nullptr;
 };
@@ -202,6 +203,7 @@ int eg_ctx_create(const eg_config* cfg, eg_ctx** out) {
   }
   if (c.blocks_per_cu < 0 || c.blocks_per_cu > 32 || c.dense_div < 0 || c.small_limit < 0 || c.small_limit > 65536 ||
       c.partition < 0 || c.partition > 2 || c.top_seeding < 0 || c.top_seeding > 1 || c.seg_edges < -1 ||
+      c.relabel < 0 || c.relabel > 2 ||
       (c.seg_edges > 0 && c.seg_edges < 256)) {
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
@@ -232,6 +234,7 @@ static void game_free(eg_game* g) {
   if (g->h_stats) (void)hipHostFree(g->h_stats);
   if (g->seed_mem) (void)hipFree(g->seed_mem);
   if (g->seg_mem) (void)hipFree(g->seg_mem);
+  if (g->perm_mem) (void)hipFree(g->perm_mem);
   if (g->h_seed) (void)hipHostFree(g->h_seed);
   for (auto& e : g->ev)
     if (e) (void)hipEventDestroy(e);
@@ -380,8 +383,39 @@ hipError_t upload_game(const eg_game_desc* d, const HostPrep& prep, DevGame& dg,
   return hipSuccess;
 }
 
+// Renumber the vertices by decreasing in-degree (ties by id) when in-degrees
+// are very skewed: the values gathered most often then share cache lines.
+static void relabel_by_indegree(const eg_game_desc& d, HostPrep& prep) {
+  const int32_t n = d.n;
+  const int64_t m = d.m;
+  std::vector<int64_t> indeg((size_t)n, 0);
+  for (int64_t e = 0; e < m; e++) indeg[(size_t)d.targets[e]]++;
+  std::vector<int32_t> order((size_t)n);
+  for (int32_t v = 0; v < n; v++) order[(size_t)v] = v;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return indeg[(size_t)a] > indeg[(size_t)b]; });
+  prep.perm.assign((size_t)n, 0);
+  for (int32_t i = 0; i < n; i++) prep.perm[(size_t)order[(size_t)i]] = i;
+  prep.r_off.assign((size_t)n + 1, 0);
+  prep.r_tgt.resize((size_t)m);
+  prep.r_w.resize((size_t)m);
+  prep.r_own.assign(((size_t)n + 7) / 8, 0);
+  std::vector<uint32_t> act(prep.act_bits.size(), 0u);
+  int64_t k = 0;
+  for (int32_t i = 0; i < n; i++) {
+    const int32_t v = order[(size_t)i];
+    for (int64_t e = d.offsets[v]; e < d.offsets[v + 1]; e++, k++) {
+      prep.r_tgt[(size_t)k] = prep.perm[(size_t)d.targets[e]];
+      prep.r_w[(size_t)k] = d.weights[e];
+    }
+    prep.r_off[(size_t)i + 1] = k;
+    if ((d.owner_bits[v >> 3] >> (v & 7)) & 1) prep.r_own[(size_t)i >> 3] |= (uint8_t)(1u << (i & 7));
+    if ((prep.act_bits[(size_t)v >> 5] >> (v & 31)) & 1u) act[(size_t)i >> 5] |= 1u << (i & 31);
+  }
+  prep.act_bits.swap(act);
+}
+
 int prepare(const eg_game_desc* desc, int bound_mode, hipStream_t s, HostPrep& prep, std::string* why,
-            uint32_t seg_edges) {
+            uint32_t seg_edges, int relabel) {
   HostCopy hc;
   eg_game_desc hd;
   int rc = host_view(desc, s, hc, hd);
@@ -391,6 +425,18 @@ int prepare(const eg_game_desc* desc, int bound_mode, hipStream_t s, HostPrep& p
   }
   rc = check_host(&hd, bound_mode, &prep.info, why, &prep.clamp, &prep.act_bits);
   if (rc != EG_OK) return rc;
+  if (relabel == 2 || (relabel == 0 && hd.n >= 4096 && hd.m > 0)) {
+    int64_t max_in = 0;
+    if (relabel == 0) {
+      std::vector<int32_t> cnt((size_t)hd.n, 0);
+      for (int64_t e = 0; e < hd.m; e++) max_in = std::max<int64_t>(max_in, ++cnt[(size_t)hd.targets[e]]);
+    }
+    // skewed: the largest in-degree is at least 64 times the average
+    if (relabel == 2 || max_in * hd.n >= 64 * hd.m) {
+      relabel_by_indegree(hd, prep);
+      hd.offsets = prep.r_off.data();
+    }
+  }
   // segments per tile for edge-balanced dense rounds (full-frontier out-degree sums)
   if (seg_edges == 0) return EG_OK;
   const int64_t ntiles = ((int64_t)hd.n + TILE_VERTICES - 1) / TILE_VERTICES;
@@ -415,7 +461,10 @@ int eg_create(eg_ctx* ctx, const eg_game_desc* desc, eg_game** out, eg_stats* st
   eg::HostPrep prep;
   std::string why;
   const uint32_t seg_edges = ctx->cfg.seg_edges < 0 ? 0u : ctx->cfg.seg_edges ? (uint32_t)ctx->cfg.seg_edges : eg::SEG_EDGES;
-  int rc = eg::prepare(desc, ctx->cfg.bound_mode, s, prep, &why, seg_edges);
+  // renumbering gathers the hubs into the first tiles, which only cut tiles
+  // spread over blocks: automatic renumbering needs unsliced, cut dense rounds
+  const int relabel = ctx->cfg.relabel == 0 && (seg_edges == 0 || ctx->cfg.partition == 2) ? 1 : ctx->cfg.relabel;
+  int rc = eg::prepare(desc, ctx->cfg.bound_mode, s, prep, &why, seg_edges, relabel);
   if (rc != EG_OK) return fail(rc, "%s", why.c_str());
 
   eg_game* g = new eg_game();
@@ -459,13 +508,23 @@ int eg_create(eg_ctx* ctx, const eg_game_desc* desc, eg_game** out, eg_stats* st
   for (auto& ev : g->ev)
     if ((e = hipEventCreate(&ev)) != hipSuccess) return cleanup_fail(EG_EDEVICE, "hipEventCreate", e);
 
+  // the game as uploaded: the caller's arrays, or their renumbered copy
+  eg_game_desc ud = *desc;
+  if (!prep.perm.empty()) {
+    ud = eg_game_desc{desc->n, desc->m, prep.r_off.data(), prep.r_tgt.data(), prep.r_w.data(), prep.r_own.data(),
+                      desc->W, EG_MEM_HOST};
+    if ((e = hipMalloc(&g->perm_mem, 4 * nn)) != hipSuccess) return cleanup_fail(EG_ENOMEM, "renumbering", e);
+    if ((e = hipMemcpyAsync(g->perm_mem, prep.perm.data(), 4 * nn, hipMemcpyHostToDevice, s)) != hipSuccess)
+      return cleanup_fail(EG_EDEVICE, "renumbering", e);
+    dg.perm = (const int32_t*)g->perm_mem;
+  }
   void* staging = nullptr;
-  if ((e = hipMalloc(&staging, eg::staging_bytes(g->n, g->m, desc->mem == EG_MEM_HOST))) != hipSuccess)
+  if ((e = hipMalloc(&staging, eg::staging_bytes(g->n, g->m, ud.mem == EG_MEM_HOST))) != hipSuccess)
     return cleanup_fail(EG_ENOMEM, "staging allocation", e);
   auto run = [&]() -> hipError_t {
     hipError_t r;
     if ((r = hipEventRecord(g->ev[0], s)) != hipSuccess) return r;
-    if ((r = eg::upload_game(desc, prep, dg, staging, s, g->ev[1])) != hipSuccess) return r;
+    if ((r = eg::upload_game(&ud, prep, dg, staging, s, g->ev[1])) != hipSuccess) return r;
     if ((r = hipEventRecord(g->ev[2], s)) != hipSuccess) return r;
     return hipStreamSynchronize(s);
   };

@@ -63,6 +63,7 @@ struct DevGame {
   const uint32_t* tile_nseg; // ntiles: segments of the tile
   uint32_t* tile_done;      // ntiles: segments of the tile finished in this round
   void* gkey;               // n keys (width vbits) combined over the segments of cut tiles
+  const int32_t* perm;      // n: internal id of each caller vertex (nullptr: ids are the caller's)
 };
 
 constexpr uint32_t SEG_EDGES = 8192;    // out-edges per segment of a cut tile (full frontier)
@@ -132,6 +133,11 @@ struct HostPrep {
   int64_t clamp;                   // largest stored weight P
   std::vector<uint32_t> act_bits;  // initially active vertices
   std::vector<uint32_t> tile_nseg; // segments per tile of TILE_VERTICES vertices (empty: no tile is cut)
+  // vertices renumbered by decreasing in-degree (perm empty: not renumbered)
+  std::vector<int32_t> perm;       // caller id -> internal id
+  std::vector<int64_t> r_off;      // the game in internal ids
+  std::vector<int32_t> r_tgt, r_w;
+  std::vector<uint8_t> r_own;
 };
 int check_host(const eg_game_desc* d, int bound_mode, eg_game_info* info, std::string* why,
                int64_t* clamp_out, std::vector<uint32_t>* act_bits);

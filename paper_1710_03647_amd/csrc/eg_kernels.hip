@@ -1310,7 +1310,7 @@ __global__ void k_output(DevGame g, int64_t* out) {
   const V* f = (const V*)g.f;
   const V top = (V)g.top;
   for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < (uint32_t)g.n; v += gridDim.x * blockDim.x) {
-    const V x = f[v];
+    const V x = f[g.perm ? (uint32_t)g.perm[v] : v];
     out[v] = x == top ? INT64_MAX : (int64_t)x;
   }
 }
@@ -1320,7 +1320,7 @@ __global__ void k_input(DevGame g, const int64_t* in) {
   V* f = (V*)g.f;
   for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < (uint32_t)g.n; v += gridDim.x * blockDim.x) {
     const int64_t x = in[v];
-    f[v] = x == INT64_MAX ? (V)g.top : (V)x;
+    f[g.perm ? (uint32_t)g.perm[v] : v] = x == INT64_MAX ? (V)g.top : (V)x;
   }
 }
 

@@ -35,7 +35,7 @@
 namespace eg {
 
 int prepare(const eg_game_desc* desc, int bound_mode, hipStream_t s, HostPrep& prep, std::string* why,
-            uint32_t seg_edges);
+            uint32_t seg_edges, int relabel);
 hipError_t launch_output(const DevGame& g, int vbits, int64_t* out, hipStream_t s);
 
 namespace {
@@ -516,7 +516,7 @@ int server_submit(Server* s, const eg_game_desc* desc, eg_ticket* out) {
   if (desc->mem != EG_MEM_HOST) return set_err(EG_EINVAL, "eg_submit takes host pointers");
   auto t = std::make_unique<Ticket>();
   std::string why;
-  int rc = prepare(desc, s->cfg.bound_mode, nullptr, t->prep, &why, 0);
+  int rc = prepare(desc, s->cfg.bound_mode, nullptr, t->prep, &why, 0, 1);
   if (rc != EG_OK) return set_err(rc, why);
   t->n = desc->n;
   t->m = desc->m;

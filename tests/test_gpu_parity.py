@@ -263,3 +263,19 @@ def test_hub_tiles_are_cut(ctx, oracle_mod):
     with eg.Context(0, top_seeding=1) as c:
         f, st = gpu_solve(c, game)
     pins.expect_equal(f, want, game.name + " seeded")
+
+
+@pytest.mark.parametrize("relabel", [1, 2])
+def test_renumbering_is_invisible(oracle_mod, relabel):
+    """Credits come back in the caller's numbering whether or not the game is
+    renumbered internally, also through set_measure and resumed solves."""
+    for game in (synth.gen_rmat(12, 16, seed=3), synth.gen_uniform(5000, 6, 40, 3)):
+        want = oracle_mod.solve(game).f
+        noise = synth.to_int(synth.draws(17, 2, 0, game.n), 0, 3 * game.W)
+        with eg.Context(0, relabel=relabel) as c:
+            with c.create(game) as g:
+                f, st, rc = g.solve()
+                pins.expect_equal(f, want, f"{game.name} relabel={relabel}")
+                g.set_measure(np.minimum(want, noise))
+                f, st, rc = g.solve(resume=True)
+                pins.expect_equal(f, want, f"{game.name} resumed, relabel={relabel}")
