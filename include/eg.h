@@ -126,6 +126,7 @@ typedef struct {
   uint64_t dense_rounds;  /* of which in the dense representation */
   uint64_t seeded;        /* vertices set to TOP by seeding passes (top_seeding) */
   uint64_t seed_passes;   /* seeding passes run */
+  uint64_t all_rounds;    /* dense rounds that lifted every vertex without activating (frontier ~ V) */
 } eg_stats;
 
 /* What eg_check derives from a valid game. */

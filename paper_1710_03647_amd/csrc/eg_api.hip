@@ -633,13 +633,15 @@ int eg_solve_ex(eg_game* g, const eg_solve_opts* opts, int64_t* credits, eg_stat
   int status = EG_OK;
   // representation of the active set: a flag sweep for large sets, a list
   // for medium ones, and for small ones a single block running many rounds
-  enum { SPARSE, DENSE, SMALL };
+  // ALL: every vertex lifted, nothing activated (while the frontier covers
+  // about every vertex; unsliced games only)
+  enum { SPARSE, DENSE, SMALL, ALL };
   auto pick = [&](uint64_t size) { return size <= small_limit ? SMALL : size >= dense_at ? DENSE : SPARSE; };
   int mode = pick(active);
   if (active && mode != DENSE) HIPCHK(eg::launch_compact(dg, 1, grid, s));
   uint32_t batch = 2;
   double t_kernels = 0;  // device time of the round kernels (back to back within a batch)
-  uint64_t dense_rounds = 0;
+  uint64_t dense_rounds = 0, all_rounds = 0;
   const bool seeding = ctx->cfg.top_seeding != 0;
   if (seeding && !g->seed_mem) {
     HIPCHK(hipMalloc(&g->seed_mem, eg::seed_bytes(g->n)));
@@ -657,7 +659,7 @@ int eg_solve_ex(eg_game* g, const eg_solve_opts* opts, int64_t* credits, eg_stat
       if (*g->h_seed) {
         // the predecessors of the new TOP vertices are flagged for round r
         seeded += *g->h_seed;
-        mode = DENSE;
+        if (mode != ALL) mode = DENSE;  // ALL rounds lift every vertex anyway
         batch = 2;
       }
     }
@@ -673,8 +675,10 @@ int eg_solve_ex(eg_game* g, const eg_solve_opts* opts, int64_t* credits, eg_stat
         if (mode == DENSE && dg.nparts > 1) {
           HIPCHK(eg::launch_partial(dg, g->vbits, r, g->part_grid, s));
           HIPCHK(eg::launch_round_parts(dg, g->vbits, r, grid, s));
-        } else if (mode == DENSE && dg.nitems) {
-          HIPCHK(eg::launch_round_seg(dg, g->vbits, r, grid, s));
+        } else if ((mode == DENSE || mode == ALL) && dg.nitems) {
+          HIPCHK(eg::launch_round_seg(dg, g->vbits, r, grid, s, mode == ALL));
+        } else if (mode == ALL) {
+          HIPCHK(eg::launch_round_all(dg, g->vbits, r, grid, s));
         } else {
           HIPCHK(eg::launch_round(dg, g->vbits, g->h, mode == DENSE, r, grid, s));
         }
@@ -682,7 +686,8 @@ int eg_solve_ex(eg_game* g, const eg_solve_opts* opts, int64_t* credits, eg_stat
     }
     HIPCHK(hipEventRecord(g->ev[4], s));
     HIPCHK(hipMemcpyAsync(g->h_ctrl, dg.ctrl, 4 * eg::C_WORDS, hipMemcpyDeviceToHost, s));
-    if (mode == DENSE) HIPCHK(hipMemcpyAsync(g->h_blk, dg.blk_chg, 4 * (size_t)grid, hipMemcpyDeviceToHost, s));
+    if (mode == DENSE || mode == ALL)
+      HIPCHK(hipMemcpyAsync(g->h_blk, dg.blk_chg, 4 * (size_t)grid, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     {
       float ms = 0;
@@ -695,17 +700,25 @@ int eg_solve_ex(eg_game* g, const eg_solve_opts* opts, int64_t* credits, eg_stat
       r = next_r;
     } else {
       launched += allowed;
-      dense_rounds += mode == DENSE ? allowed : 0;
+      dense_rounds += mode == DENSE || mode == ALL ? allowed : 0;
+      all_rounds += mode == ALL ? allowed : 0;
     }
     int next_mode = mode;
-    if (mode == DENSE) {
+    if (mode == DENSE || mode == ALL) {
       if (g->h_ctrl[eg::C_ANY0 + (r - 1) % 3] == 0) break;  // nothing rose in the last round
       uint64_t changed = 0;
       for (int b = 0; b < grid; b++) changed += g->h_blk[b];
       // predecessors of the changed vertices, at most
       const double est = (double)changed * g->avg_indeg;
-      if (est <= (double)small_limit) next_mode = SMALL;
-      else if (est < (double)dense_at / 4) next_mode = SPARSE;
+      if (mode == ALL) {
+        if (est < (double)g->n / 2) next_mode = DENSE;
+      } else if (est >= (double)g->n && dg.nparts == 1) {
+        next_mode = ALL;
+      } else if (est <= (double)small_limit) {
+        next_mode = SMALL;
+      } else if (est < (double)dense_at / 4) {
+        next_mode = SPARSE;
+      }
     } else {
       const uint64_t next = g->h_ctrl[eg::C_CNT0 + r % 3];
       if (next == 0) break;
@@ -716,7 +729,15 @@ int eg_solve_ex(eg_game* g, const eg_solve_opts* opts, int64_t* credits, eg_stat
       break;
     }
     if (next_mode != mode) {
-      if (mode == DENSE) HIPCHK(eg::launch_compact(dg, r, grid, s));
+      if (mode == DENSE && next_mode != ALL) HIPCHK(eg::launch_compact(dg, r, grid, s));
+      if (mode == ALL) {
+        // ALL rounds activate nothing: the round that follows lifts every
+        // vertex again, this time activating the predecessors of changes
+        uint8_t* act_r = (r & 1) ? dg.act1 : dg.act0;
+        uint8_t* act_n = (r & 1) ? dg.act0 : dg.act1;
+        HIPCHK(hipMemsetAsync(act_r, 1, (size_t)g->n, s));
+        HIPCHK(hipMemsetAsync(act_n, 0, (size_t)g->n, s));
+      }
       mode = next_mode;
       batch = 2;
     } else if (batch < 64) {
@@ -759,6 +780,7 @@ int eg_solve_ex(eg_game* g, const eg_solve_opts* opts, int64_t* credits, eg_stat
     st->seeded = seeded;
     st->seed_passes = seed_passes;
     st->dense_rounds = dense_rounds;
+    st->all_rounds = all_rounds;
   }
   if (status != EG_OK) return fail(status, "budget exhausted after %llu rounds", (unsigned long long)launched);
   return EG_OK;

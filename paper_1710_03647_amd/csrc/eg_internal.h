@@ -149,7 +149,8 @@ hipError_t upload_game(const eg_game_desc* d, const HostPrep& prep, DevGame& dg,
                        hipEvent_t after_layout);
 hipError_t launch_epoch(const BatchTable& bt, int grid, hipStream_t s);
 hipError_t launch_batch_small(const BatchTable& bt, uint32_t max_rounds, hipStream_t s);
-hipError_t launch_round_seg(const DevGame& g, int vbits, uint32_t r, int grid, hipStream_t s);
+hipError_t launch_round_seg(const DevGame& g, int vbits, uint32_t r, int grid, hipStream_t s, bool all);
+hipError_t launch_round_all(const DevGame& g, int vbits, uint32_t r, int grid, hipStream_t s);
 hipError_t launch_gkey_init(const DevGame& g, int vbits, hipStream_t s);
 
 // Layout and predecessor lists (eg_kernels.hip)

@@ -518,7 +518,11 @@ struct Counters {
 // flattened the same way.  Any degree distribution is balanced across the
 // block.  Returns with the shared arrays still in use: the caller
 // synchronises before the next tile.
-template <typename V, bool DENSE, bool PART = false>
+// ALL (dense only): every vertex is lifted and nothing is activated; used
+// while the frontier covers (nearly) every vertex, where lifting all costs
+// less than sweeping flags and activating predecessors.  A lift whose inputs
+// did not change leaves its value unchanged, so the result is the same.
+template <typename V, bool DENSE, bool PART = false, bool ALL = false>
 __device__ __forceinline__ void round_tile(const DevGame& g, RoundShared<V>& sh, uint32_t r, uint32_t t,
                                            uint32_t items, Counters& c) {
   const uint32_t tid = threadIdx.x;
@@ -533,18 +537,21 @@ __device__ __forceinline__ void round_tile(const DevGame& g, RoundShared<V>& sh,
   const uint32_t idx = t * TILE + tid;
   int32_t v = -1;
   if (idx < items) {
-    if (DENSE) v = act_cur[idx] ? (int32_t)idx : -1;
+    if (ALL) v = (int32_t)idx;
+    else if (DENSE) v = act_cur[idx] ? (int32_t)idx : -1;
     else v = wl_in[idx];
   }
   uint32_t raw = 0, deg = 0, pb = 0, pe = 0;
   V old = 0;
   if (v >= 0) {
-    act_cur[v] = 0;  // consumed
+    if (!ALL) act_cur[v] = 0;  // consumed
     raw = load_stream(g.rs + v);
     deg = (load_stream(g.rs + v + 1) & ROW_MASK) - (raw & ROW_MASK);
     old = f[v];
-    pb = load_stream(g.rev_off + v);
-    pe = load_stream(g.rev_off + v + 1);
+    if (!ALL) {
+      pb = load_stream(g.rev_off + v);
+      pe = load_stream(g.rev_off + v + 1);
+    }
   }
   uint32_t E;
   const uint32_t ex = block_excl_scan(deg, sh.wsum, &E);
@@ -598,6 +605,7 @@ __device__ __forceinline__ void round_tile(const DevGame& g, RoundShared<V>& sh,
       ideg = pe - pb;
     }
   }
+  if (ALL) return;
   uint32_t P;
   const uint32_t pex = block_excl_scan(ideg, sh.wsum, &P);
   sh.ppre[tid] = pex;
@@ -654,7 +662,7 @@ __device__ __forceinline__ void slice_edges(const DevGame& g, V* key, const uint
 // atomic min, and the block that finishes the tile's last segment (a counter
 // per tile) completes the round for the whole tile from gkey: the new values,
 // the flag clearing and the predecessor activation.
-template <typename V>
+template <typename V, bool ALL = false>
 __device__ __forceinline__ void round_seg(const DevGame& g, RoundShared<V>& sh, uint32_t r, uint32_t t,
                                           uint32_t seg, uint32_t nseg, Counters& c, uint32_t& s_last) {
   const uint32_t tid = threadIdx.x;
@@ -665,15 +673,17 @@ __device__ __forceinline__ void round_seg(const DevGame& g, RoundShared<V>& sh, 
   uint8_t* act_next = (r & 1) ? g.act0 : g.act1;
   const uint32_t idx = t * TILE + tid;
   int32_t v = -1;
-  if (idx < (uint32_t)g.n && act_cur[idx]) v = (int32_t)idx;
+  if (idx < (uint32_t)g.n && (ALL || act_cur[idx])) v = (int32_t)idx;
   uint32_t raw = 0, deg = 0, pb = 0, pe = 0;
   V old = 0;
   if (v >= 0) {
     raw = load_stream(g.rs + v);
     deg = (load_stream(g.rs + v + 1) & ROW_MASK) - (raw & ROW_MASK);
     old = f[v];
-    pb = load_stream(g.rev_off + v);
-    pe = load_stream(g.rev_off + v + 1);
+    if (!ALL) {
+      pb = load_stream(g.rev_off + v);
+      pe = load_stream(g.rev_off + v + 1);
+    }
   }
   uint32_t E;
   const uint32_t ex = block_excl_scan(deg, sh.wsum, &E);
@@ -723,7 +733,7 @@ __device__ __forceinline__ void round_seg(const DevGame& g, RoundShared<V>& sh, 
   }
   uint32_t ideg = 0;
   if (v >= 0) {
-    act_cur[v] = 0;  // consumed
+    if (!ALL) act_cur[v] = 0;  // consumed
     V nv = (raw & OWNER_BIT) ? -k : k;
     if (nv > bound) nv = top;
     if (nv < old) nv = old;  // writes never lower a value (see round_tile)
@@ -735,6 +745,7 @@ __device__ __forceinline__ void round_seg(const DevGame& g, RoundShared<V>& sh, 
       ideg = pe - pb;
     }
   }
+  if (ALL) return;
   uint32_t P;
   const uint32_t pex = block_excl_scan(ideg, sh.wsum, &P);
   sh.ppre[tid] = pex;
@@ -757,7 +768,7 @@ __device__ __forceinline__ void round_seg(const DevGame& g, RoundShared<V>& sh, 
 }
 
 // A dense round over the segments of the tiles (see round_seg).
-template <typename V>
+template <typename V, bool ALL = false>
 __global__ __launch_bounds__(BLOCK) void k_round_seg(DevGame g, uint32_t r) {
   __shared__ RoundShared<V> sh;
   __shared__ uint32_t s_last;
@@ -777,7 +788,7 @@ __global__ __launch_bounds__(BLOCK) void k_round_seg(DevGame g, uint32_t r) {
   for (uint32_t x = blockIdx.x; x < items; x += gridDim.x) {
     block_sync();  // the previous item is done with the shared arrays
     const uint32_t t = g.item_tile[x];
-    round_seg<V>(g, sh, r, t, g.item_seg[x], g.tile_nseg[t], c, s_last);
+    round_seg<V, ALL>(g, sh, r, t, g.item_seg[x], g.tile_nseg[t], c, s_last);
   }
   block_counters(sh, c);
   if (tid < S_WORDS) g.slots[blockIdx.x * S_WORDS + tid] += sh.st[tid];
@@ -855,7 +866,7 @@ __device__ __forceinline__ void block_counters(RoundShared<V>& sh, const Counter
 
 // One round of Alg. 3 over L_r of one game: blocks take the tiles of the
 // active set in turn (see round_tile).
-template <typename V, bool DENSE, bool PART = false>
+template <typename V, bool DENSE, bool PART = false, bool ALL = false>
 __global__ __launch_bounds__(BLOCK) void k_round(DevGame g, uint32_t r) {
   __shared__ RoundShared<V> sh;
   const uint32_t tid = threadIdx.x;
@@ -877,7 +888,7 @@ __global__ __launch_bounds__(BLOCK) void k_round(DevGame g, uint32_t r) {
   const uint32_t ntiles = (items + TILE - 1) / TILE;
   for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     block_sync();  // the previous tile is done with the shared arrays
-    round_tile<V, DENSE, PART>(g, sh, r, t, items, c);
+    round_tile<V, DENSE, PART, ALL>(g, sh, r, t, items, c);
   }
   block_counters(sh, c);
   if (!DENSE) {
@@ -1364,9 +1375,20 @@ hipError_t launch_round(const DevGame& g, int vbits, int h, bool dense, uint32_t
   return hipGetLastError();
 }
 
-hipError_t launch_round_seg(const DevGame& g, int vbits, uint32_t r, int grid, hipStream_t s) {
-  if (vbits == 32) hipLaunchKernelGGL(k_round_seg<int32_t>, dim3(grid), dim3(BLOCK), 0, s, g, r);
-  else hipLaunchKernelGGL(k_round_seg<int64_t>, dim3(grid), dim3(BLOCK), 0, s, g, r);
+hipError_t launch_round_seg(const DevGame& g, int vbits, uint32_t r, int grid, hipStream_t s, bool all) {
+  if (vbits == 32) {
+    if (all) hipLaunchKernelGGL((k_round_seg<int32_t, true>), dim3(grid), dim3(BLOCK), 0, s, g, r);
+    else hipLaunchKernelGGL((k_round_seg<int32_t, false>), dim3(grid), dim3(BLOCK), 0, s, g, r);
+  } else {
+    if (all) hipLaunchKernelGGL((k_round_seg<int64_t, true>), dim3(grid), dim3(BLOCK), 0, s, g, r);
+    else hipLaunchKernelGGL((k_round_seg<int64_t, false>), dim3(grid), dim3(BLOCK), 0, s, g, r);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_round_all(const DevGame& g, int vbits, uint32_t r, int grid, hipStream_t s) {
+  if (vbits == 32) hipLaunchKernelGGL((k_round<int32_t, true, false, true>), dim3(grid), dim3(BLOCK), 0, s, g, r);
+  else hipLaunchKernelGGL((k_round<int64_t, true, false, true>), dim3(grid), dim3(BLOCK), 0, s, g, r);
   return hipGetLastError();
 }
 

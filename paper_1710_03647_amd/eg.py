@@ -62,7 +62,8 @@ class eg_stats(ctypes.Structure):
                 ("model_bytes", ctypes.c_double), ("achieved_gbps", ctypes.c_double),
                 ("t_round_kernels", ctypes.c_double), ("t_queue", ctypes.c_double),
                 ("t_latency", ctypes.c_double), ("launched_rounds", ctypes.c_uint64),
-                ("dense_rounds", ctypes.c_uint64), ("seeded", ctypes.c_uint64), ("seed_passes", ctypes.c_uint64)]
+                ("dense_rounds", ctypes.c_uint64), ("seeded", ctypes.c_uint64), ("seed_passes", ctypes.c_uint64),
+                ("all_rounds", ctypes.c_uint64)]
 
     def to_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
