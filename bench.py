@@ -324,7 +324,7 @@ def main():
                    "rounds_per_step": agg["rounds"] / steps, "launch_shape": shape},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
-                     "kernel": "k_round (lift + predecessor activation, one launch per round)",
+                     "kernel": "round kernels of the solve (one launch per round; all-vertex dense rounds dominate)",
                      "bytes_per_launch": agg["model_bytes"] / max(1, agg["launched_rounds"]),
                      "us_per_launch": agg["t_round_kernels"] / max(1, agg["launched_rounds"]) * 1e6},
     }
