@@ -493,6 +493,7 @@ int eg_create(eg_ctx* ctx, const eg_game_desc* desc, eg_game** out, eg_stats* st
   g->out64 = (int64_t*)((char*)g->arena + L.off[eg::L_OUT]);
   dg.bound = g->bound;
   dg.top = g->bound + prep.clamp + 1;
+  dg.lanes_ok = eg::lanes_ok_for(g->n, g->m, g->vbits);
   g->avg_indeg = (double)g->m / (double)nn;
 
   auto cleanup_fail = [&](int code, const char* what, hipError_t err) {

@@ -64,7 +64,15 @@ struct DevGame {
   uint32_t* tile_done;      // ntiles: segments of the tile finished in this round
   void* gkey;               // n keys (width vbits) combined over the segments of cut tiles
   const int32_t* perm;      // n: internal id of each caller vertex (nullptr: ids are the caller's)
+  uint32_t lanes_ok;        // small-degree tiles may use one lane per vertex (game fits the caches)
 };
+
+// A game whose edges and values fit in this many bytes may lift small-degree
+// tiles with one lane per vertex.
+constexpr size_t LANES_BYTES = (size_t)64 << 20;
+inline uint32_t lanes_ok_for(int32_t n, int64_t m, int vbits) {
+  return (size_t)m * 8 + (size_t)n * (size_t)(vbits / 8) <= LANES_BYTES ? 1u : 0u;
+}
 
 constexpr uint32_t SEG_EDGES = 8192;    // out-edges per segment of a cut tile (full frontier)
 

@@ -282,6 +282,7 @@ hipError_t launch_reverse_csr(const uint32_t* rs, const int2* edges, int32_t n, 
 
 constexpr int TILE = TILE_VERTICES;  // list entries / vertices per tile
 static_assert(TILE == BLOCK, "one tile entry per thread");
+static_assert(BLOCK / WAVE == 4, "four waves per block (wbig)");
 constexpr int UNROLL = 8;           // edges (or predecessor entries) per thread in flight
 constexpr int PUSH_CAP = 2048;      // staged list entries per block (sparse rounds)
 
@@ -340,6 +341,7 @@ struct RoundShared {
   uint32_t ppre[BLOCK + 1];  // exclusive prefix of in-degrees of the tile's changed vertices
   uint32_t pbeg[BLOCK];      // their predecessor-list starts
   uint32_t wsum[BLOCK / WAVE];
+  uint32_t wbig[BLOCK / WAVE];  // per wave: some active vertex has more than LANE_DEG out-edges
   int32_t push[PUSH_CAP];    // sparse: staged entries of L_{r+1}
   unsigned long long st[S_WORDS];
   uint32_t n_push, base;
@@ -518,6 +520,49 @@ struct Counters {
 // flattened the same way.  Any degree distribution is balanced across the
 // block.  Returns with the shared arrays still in use: the caller
 // synchronises before the next tile.
+constexpr uint32_t LANE_DEG = 32;  // tiles whose active vertices have at most this many out-edges
+constexpr int LANE_UNROLL = 8;      // use one lane per vertex, this many edges in flight per lane
+                                    // (games that fit the caches, DevGame::lanes_ok: a lane's row
+                                    // loads are not coalesced across the wave, which costs more than
+                                    // the search and LDS folding they save once rows come from HBM)
+
+// One lane per active vertex (tiles of small out-degrees): the lane walks its
+// own row, LANE_UNROLL edges at a time, loads first and gathers second, and
+// keeps the running key in a register.  No edge-to-vertex search and no LDS
+// atomics.  The trip count is the wave's largest degree; lanes past their own
+// degree re-read their last edge and contribute nothing.
+template <typename V>
+__device__ __forceinline__ V lift_lanes(const DevGame& g, const V* f, int32_t v, uint32_t raw, uint32_t deg) {
+  const bool neg = (raw & OWNER_BIT) != 0;
+  V k = neg ? V(0) : std::numeric_limits<V>::max();
+  uint32_t dmax = deg;
+#pragma unroll
+  for (int o = 1; o < WAVE; o <<= 1) {
+    const uint32_t y = __shfl_xor(dmax, o, WAVE);
+    dmax = y > dmax ? y : dmax;
+  }
+  const uint32_t e0 = raw & ROW_MASK;
+  for (uint32_t j0 = 0; j0 < dmax; j0 += LANE_UNROLL) {
+    int2 ed[LANE_UNROLL];
+#pragma unroll
+    for (int jj = 0; jj < LANE_UNROLL; jj++) {
+      const uint32_t j = j0 + jj;
+      ed[jj] = load_edge(g.edges, v >= 0 ? e0 + (j < deg ? j : deg - 1) : 0u);
+    }
+    V fu[LANE_UNROLL];
+#pragma unroll
+    for (int jj = 0; jj < LANE_UNROLL; jj++) fu[jj] = f[ed[jj].x];
+#pragma unroll
+    for (int jj = 0; jj < LANE_UNROLL; jj++) {
+      V tm = fu[jj] - (V)ed[jj].y;
+      tm = tm > V(0) ? tm : V(0);
+      const V key = neg ? -tm : tm;
+      if (j0 + jj < deg && key < k) k = key;
+    }
+  }
+  return k;
+}
+
 // ALL (dense only): every vertex is lifted and nothing is activated; used
 // while the frontier covers (nearly) every vertex, where lifting all costs
 // less than sweeping flags and activating predecessors.  A lift whose inputs
@@ -553,8 +598,11 @@ __device__ __forceinline__ void round_tile(const DevGame& g, RoundShared<V>& sh,
       pe = load_stream(g.rev_off + v + 1);
     }
   }
+  const bool wave_big = __ballot(deg > LANE_DEG) != 0;  // every lane takes part in the ballot
+  if (lane_id() == 0) sh.wbig[tid / WAVE] = wave_big;
   uint32_t E;
-  const uint32_t ex = block_excl_scan(deg, sh.wsum, &E);
+  const uint32_t ex = block_excl_scan(deg, sh.wsum, &E);  // its barrier also publishes wbig
+  const bool lanes = g.lanes_ok && !(sh.wbig[0] | sh.wbig[1] | sh.wbig[2] | sh.wbig[3]);
   sh.epre[tid] = ex;
   if (tid == BLOCK - 1) sh.epre[BLOCK] = E;
   sh.ebeg[tid] = raw;
@@ -572,7 +620,9 @@ __device__ __forceinline__ void round_tile(const DevGame& g, RoundShared<V>& sh,
   block_sync();
   if (E == 0) return;  // block-uniform: no active vertex in this tile
 
-  if (!PART)
+  if (!PART && lanes) {
+    sh.key[tid] = lift_lanes<V>(g, f, v, raw, deg);
+  } else if (!PART) {
     for (uint32_t x0 = 0; x0 < E; x0 += BLOCK * UNROLL) {
       switch (std::min<uint32_t>((E - x0 + BLOCK - 1) / BLOCK, UNROLL)) {
         case 1: lift_edges<V, 1>(g, sh, f, x0, E); break;
@@ -585,6 +635,7 @@ __device__ __forceinline__ void round_tile(const DevGame& g, RoundShared<V>& sh,
         default: lift_edges<V, UNROLL>(g, sh, f, x0, E); break;
       }
     }
+  }
   block_sync();
 
   uint32_t ideg = 0;
@@ -685,8 +736,11 @@ __device__ __forceinline__ void round_seg(const DevGame& g, RoundShared<V>& sh, 
       pe = load_stream(g.rev_off + v + 1);
     }
   }
+  const bool wave_big = __ballot(deg > LANE_DEG) != 0;  // every lane takes part in the ballot
+  if (lane_id() == 0) sh.wbig[tid / WAVE] = wave_big;
   uint32_t E;
-  const uint32_t ex = block_excl_scan(deg, sh.wsum, &E);
+  const uint32_t ex = block_excl_scan(deg, sh.wsum, &E);  // its barrier also publishes wbig
+  const bool lanes = g.lanes_ok && nseg == 1 && !(sh.wbig[0] | sh.wbig[1] | sh.wbig[2] | sh.wbig[3]);
   sh.epre[tid] = ex;
   if (tid == BLOCK - 1) sh.epre[BLOCK] = E;
   sh.ebeg[tid] = raw;
@@ -695,7 +749,8 @@ __device__ __forceinline__ void round_seg(const DevGame& g, RoundShared<V>& sh, 
   block_sync();
   if (E == 0) return;  // block-uniform, and the same in every segment block of the tile
   const uint32_t lo = (uint32_t)((uint64_t)E * seg / nseg), hi = (uint32_t)((uint64_t)E * (seg + 1) / nseg);
-  for (uint32_t x0 = lo; x0 < hi; x0 += BLOCK * UNROLL) {
+  if (lanes) sh.key[tid] = lift_lanes<V>(g, f, v, raw, deg);
+  for (uint32_t x0 = lo; x0 < (lanes ? lo : hi); x0 += BLOCK * UNROLL) {
     switch (std::min<uint32_t>((hi - x0 + BLOCK - 1) / BLOCK, UNROLL)) {
       case 1: lift_edges<V, 1>(g, sh, f, x0, hi); break;
       case 2: lift_edges<V, 2>(g, sh, f, x0, hi); break;

@@ -295,6 +295,7 @@ int Server::admit_one(Ticket* t) {
   bind_layout(dg, base, L, t->n, t->m, vbits);
   dg.bound = t->prep.info.bound;
   dg.top = dg.bound + t->prep.clamp + 1;
+  dg.lanes_ok = lanes_ok_for(t->n, t->m, vbits);
   t->out64 = (int64_t*)(base + L.off[L_OUT]);
   eg_game_desc d{t->n, t->m, t->off.data(), t->tgt.data(), t->w.data(), t->own.data(), t->W, EG_MEM_HOST};
   void* staging = base + align_up(L.total);
