@@ -113,7 +113,7 @@ def tune(game, device: int = 0, path: str = TABLE, space: dict | None = None, ve
     best_t, best = results[0]
     table = load_table(path)
     table[key] = {"config": best, "proxy_seconds": best_t,
-                  "default_seconds": next((t for t, c in results if c == DEFAULTS), None),
+                  "default_seconds": next((t for t, c in results if all(c[k] == DEFAULTS[k] for k in c)), None),
                   "proxy": getattr(proxy, "name", ""), "rounds": rounds or "to the fixpoint"}
     with open(path, "w") as fh:
         json.dump(table, fh, indent=1, sort_keys=True)
