@@ -14,8 +14,11 @@
  * above the bound B become TOP; B = (n-1)*W by default, or M_G (Sec. 3.1).  The
  * device iteration follows the frontier scheme of Alg. 3: each round lifts the
  * active vertices in parallel, in place, and the predecessors of every vertex
- * whose value changed form the next active set.  All arithmetic is integer, so
- * the result equals the sequential worklist of Alg. 1 bit for bit.
+ * whose value changed form the next active set (while that set covers about
+ * every vertex, rounds lift every vertex instead).  Optionally, cycles that
+ * player 1 can force with negative weight are set to TOP between rounds
+ * (Lemma 1), which changes the work but not the result.  All arithmetic is
+ * integer, so the result equals the sequential worklist of Alg. 1 bit for bit.
  *
  * Output: credits[v] = c(v) for v won by player 0, EG_TOP for v won by player 1.
  *
@@ -147,7 +150,7 @@ typedef struct {
   int resume;             /* 0: start from f = 0 with the initial active set of Alg. 3.
                              1: start from the game's current f with every vertex active
                                 (any f below the least fixpoint reaches it). */
-  int driver;             /* 0 = automatic; see eg_solve_ex */
+  int driver;             /* reserved: must be 0 (EG_EINVAL otherwise) */
 } eg_solve_opts;
 
 /* Create a context on cfg->device (NULL cfg = all defaults).  Returns EG_EDEVICE
@@ -205,8 +208,9 @@ int eg_cancel(eg_ctx* ctx, eg_ticket t);
 int eg_wait(eg_ctx* ctx, eg_ticket t, int64_t* credits, eg_stats* stats, double timeout_s);
 
 /* Batching: solve `count` games together in the batched device iteration
- * (all resident games advance one round per launch, each retired at its own
- * fixpoint) and block until all are done.  credits[i] receives game i's n
+ * (resident games advance one round per launch together, or many rounds per
+ * launch on their own once their active set is small; each is retired at its
+ * own fixpoint) and block until all are done.  credits[i] receives game i's n
  * credits; stats (nullable) count entries.  The games must fit the context's
  * HBM budget one at a time; they are admitted as room frees up. */
 int eg_solve_batch(eg_ctx* ctx, const eg_game_desc* games, int count, int64_t* const* credits, eg_stats* stats);

@@ -610,6 +610,7 @@ int eg_solve_ex(eg_game* g, const eg_solve_opts* opts, int64_t* credits, eg_stat
   if (!g) return fail(EG_EINVAL, "null game");
   eg_solve_opts o{};
   if (opts) o = *opts;
+  if (o.driver != 0) return fail(EG_EINVAL, "eg_solve_opts.driver is reserved and must be 0");
   eg_ctx* ctx = g->ctx;
   const uint64_t max_rounds = o.max_rounds ? o.max_rounds : ctx->cfg.max_rounds;
   const double budget = o.time_budget_s > 0 ? o.time_budget_s : ctx->cfg.time_budget_s;
