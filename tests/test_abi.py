@@ -127,3 +127,30 @@ def test_no_device_fails_loudly():
     with pytest.raises(eg.EgError) as ei:
         eg.Context(0)
     assert ei.value.code == eg.EG_EDEVICE
+
+
+def _header_fields(struct_name):
+    """Field names of a typedef struct in eg.h, in order."""
+    text = open(eg.HEADER).read()
+    end = re.search(r"\}\s*" + struct_name + ";", text).start()
+    start = text.rindex("typedef struct {", 0, end) + len("typedef struct {")
+    body = re.sub(r"/\*.*?\*/", "", text[start:end], flags=re.S)
+    return [re.findall(r"(\w+)\s*$", decl.strip())[0] for decl in body.split(";") if decl.strip()]
+
+
+@pytest.mark.parametrize("struct_name,cls", [("eg_config", eg.eg_config), ("eg_stats", eg.eg_stats),
+                                             ("eg_solve_opts", eg.eg_solve_opts),
+                                             ("eg_game_desc", eg.eg_game_desc), ("eg_game_info", eg.eg_game_info)])
+def test_binding_structs_match_header(struct_name, cls):
+    """The ctypes mirrors of the header's structs list the same fields in the
+    same order (fields are only ever appended)."""
+    assert [f for f, _ in cls._fields_] == _header_fields(struct_name)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+
+    r = subprocess.run([sys.executable, eg.os.path.join(eg.os.path.dirname(eg.PKG), "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
