@@ -279,3 +279,19 @@ def test_renumbering_is_invisible(oracle_mod, relabel):
                 g.set_measure(np.minimum(want, noise))
                 f, st, rc = g.solve(resume=True)
                 pins.expect_equal(f, want, f"{game.name} resumed, relabel={relabel}")
+
+
+SHAPES = [dict(), dict(blocks_per_cu=4), dict(blocks_per_cu=16, dense_div=4), dict(small_limit=64),
+          dict(small_limit=8192, dense_div=256), dict(seg_edges=256), dict(seg_edges=-1, relabel=1),
+          dict(partition=2), dict(relabel=2, seg_edges=512)]
+
+
+def test_launch_shapes_give_identical_credits(oracle_mod):
+    """The credits do not depend on the launch shape: occupancy, representation
+    thresholds, tile cutting, renumbering and slicing (bit-identical results)."""
+    for game in (synth.gen_rmat(13, 16, seed=7), synth.gen_uniform(9999, 7, 80, 29)):
+        want = oracle_mod.solve(game).f
+        for shape in SHAPES:
+            with eg.Context(0, **shape) as c:
+                f, st = gpu_solve(c, game)
+            pins.expect_equal(f, want, f"{game.name} {shape}")
