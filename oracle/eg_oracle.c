@@ -306,3 +306,29 @@ int64_t orc_count_unstable(int32_t n, const int64_t *off, const int32_t *tgt, co
     if (lift_value(v, off, tgt, w, owner, f, bound) != f[v]) bad++;
   return bad;
 }
+
+/* Player 0's positional strategy read off a progress measure f (Def. 5, first
+ * condition; Lemma 1).  For v in V0 with f(v) finite, choice[v] is the least k
+ * such that the edge e = off[v] + k satisfies f(v) >= f(target(e)) (-) w(e)
+ * (TOP is above every finite value); -1 for player-1 vertices and where
+ * f(v) = TOP.  When f is the least progress measure, following these edges
+ * keeps the energy of every play from v >= 0 given the initial credit f(v).
+ * Returns the number of V0 vertices with finite f(v) and no such edge (0 for
+ * a progress measure); those get -1 as well. */
+int64_t orc_strategy(int32_t n, const int64_t *off, const int32_t *tgt, const int32_t *w,
+                     const uint8_t *owner, int64_t bound, const int64_t *f, int32_t *choice) {
+  int64_t missing = 0;
+  for (int32_t v = 0; v < n; v++) {
+    choice[v] = -1;
+    if (owner[v] != 0 || f[v] == ORC_TOP) continue;
+    for (int64_t e = off[v]; e < off[v + 1]; e++) {
+      int64_t term = clamp_to_codomain(ominus(f[tgt[e]], (int64_t)w[e]), bound);
+      if (term != ORC_TOP && term <= f[v]) {
+        choice[v] = (int32_t)(e - off[v]);
+        break;
+      }
+    }
+    if (choice[v] < 0) missing++;
+  }
+  return missing;
+}

@@ -76,6 +76,10 @@ def _load(path: str | None = None):
                                            p(ctypes.c_int32), p(ctypes.c_uint8), ctypes.c_int64,
                                            p(ctypes.c_int64)]
         lib.orc_count_unstable.restype = ctypes.c_int64
+        lib.orc_strategy.argtypes = [ctypes.c_int32, p(ctypes.c_int64), p(ctypes.c_int32),
+                                     p(ctypes.c_int32), p(ctypes.c_uint8), ctypes.c_int64,
+                                     p(ctypes.c_int64), p(ctypes.c_int32)]
+        lib.orc_strategy.restype = ctypes.c_int64
         _libs[key] = lib
     return lib
 
@@ -135,3 +139,24 @@ def count_unstable(game, f: np.ndarray, bound: int, lib_path: str | None = None)
                                       _ptr(tgt, ctypes.c_int32), _ptr(w, ctypes.c_int32),
                                       _ptr(owner, ctypes.c_uint8), int(bound),
                                       _ptr(fa, ctypes.c_int64)))
+
+
+def strategy(game, f: np.ndarray, bound: int | None = None, lib_path: str | None = None):
+    """Player 0's positional strategy from the progress measure ``f`` (Def. 5, Lemma 1).
+
+    Returns (choice, missing): choice[v] is the index, within v's out-edges, of
+    the first edge e with f(v) >= f(target) (-) w(e), for player-0 vertices with
+    finite f(v), else -1; missing counts player-0 vertices with finite f(v) and
+    no such edge (0 when f is a progress measure).  ``bound`` defaults to (n-1)W.
+    """
+    lib = _load(lib_path)
+    off, tgt, w, owner = _arrays(game)
+    n = int(game.n)
+    if bound is None:
+        bound = bound_of(game, lib_path=lib_path)
+    fa = np.ascontiguousarray(f, dtype=np.int64)
+    choice = np.empty(max(n, 1), dtype=np.int32)
+    missing = lib.orc_strategy(n, _ptr(off, ctypes.c_int64), _ptr(tgt, ctypes.c_int32),
+                               _ptr(w, ctypes.c_int32), _ptr(owner, ctypes.c_uint8), int(bound),
+                               _ptr(fa, ctypes.c_int64), _ptr(choice, ctypes.c_int32))
+    return choice[:n], int(missing)

@@ -260,3 +260,68 @@ def medium_games():
         synth.gen_rmat(9, 8, wlim=50, seed=3),
         synth.gen_uniform(700, 3, 5, 13),
     ]
+
+
+# --------------------------------------------------------------------------- strategy (Lemma 1)
+def _sigma_dict(game, choice):
+    """Full positional strategy {v: edge index}: the given choice, else v's first edge."""
+    return {v: int(game.off[v]) + max(0, int(choice[v])) for v in range(game.n) if game.owner[v] == 0}
+
+
+def _credit_under(game, sigma, v):
+    """Credit player 0 needs at v when playing sigma: None if a negative cycle is
+    reachable from v in G(sigma) (Lemma 1), else the worst deficit over the
+    simple paths from v."""
+    adj = brute._induced_edges(game, sigma)
+    reach = brute._reachable(adj, v)
+    if any(brute._has_negative_cycle_through(adj, u, set(range(game.n))) for u in reach):
+        return None
+    return brute._worst_deficit(adj, v)
+
+
+def pin_strategy_brute(strategy, count=600, n_max=6, deg_max=3, wlim=4, seed0=90_000):
+    """``strategy(game, f) -> choice`` on tiny games, against brute force over G(sigma0):
+    * choice is -1 exactly on player-1 vertices and on TOP vertices;
+    * from every v in W0 the chosen strategy wins (no negative cycle reachable,
+      Lemma 1) with credit exactly f(v) (Def. 4: f(v) is the least credit);
+    * at every player-0 v in W0, each earlier out-edge, played instead, needs more
+      than f(v) or loses (the choice is the first edge that achieves f(v))."""
+    for s in range(count):
+        g = synth.gen_random_small(seed0 + s, n_max=n_max, deg_max=deg_max, wlim=wlim)
+        f = brute.credits_fw(g)
+        choice = np.asarray(strategy(g, f))
+        what = f"strategy seed={seed0 + s} n={g.n}"
+        want_neg = (g.owner == 1) | (f == TOP)
+        if not np.array_equal(choice < 0, want_neg):
+            raise AssertionError(f"{what}: choice {choice.tolist()} f {fmt(f)} owner {g.owner.tolist()}")
+        if np.any(choice >= np.diff(g.off)):
+            raise AssertionError(f"{what}: choice past the row end {choice.tolist()}")
+        sigma = _sigma_dict(g, choice)
+        for v in range(g.n):
+            if f[v] == TOP:
+                continue
+            c = _credit_under(g, sigma, v)
+            if c is None or c != f[v]:
+                raise AssertionError(f"{what}: v={v} needs {c} under the strategy, f={f[v]}")
+            if g.owner[v] == 0:
+                for k in range(int(choice[v])):
+                    alt = dict(sigma)
+                    alt[v] = int(g.off[v]) + k
+                    ca = _credit_under(g, alt, v)
+                    if ca is not None and ca <= f[v]:
+                        raise AssertionError(f"{what}: v={v} edge {k} < choice {choice[v]} also needs only {ca}")
+
+
+def pin_strategy_cases(strategy):
+    """Hand cases: two edges into 0-sinks with weights (a, b); a trap; a player-1 vertex."""
+    for a, b, want in [(-3, -1, 1), (-1, -1, 0), (-1, -3, 0), (2, 5, 0), (-4, 0, 1)]:
+        g = synth.make_game(3, [(0, 1, a), (0, 2, b), (1, 1, 0), (2, 2, 0)], [0, 0, 0], W=4)
+        f = np.array([max(0, -max(a, b)), 0, 0], dtype=np.int64)
+        got = np.asarray(strategy(g, f))
+        if got.tolist() != [want, 0, 0]:
+            raise AssertionError(f"strategy a={a} b={b}: got {got.tolist()} want {[want, 0, 0]}")
+    # 1 is a -1 self-loop trap (TOP); 0 must avoid it through its second edge
+    g = synth.make_game(3, [(0, 1, 5), (0, 2, -2), (1, 1, -1), (2, 2, 0)], [0, 0, 1], W=2)
+    got = np.asarray(strategy(g, np.array([2, TOP, 0], dtype=np.int64)))
+    if got.tolist() != [1, -1, -1]:
+        raise AssertionError(f"strategy trap: got {got.tolist()} want [1, -1, -1]")

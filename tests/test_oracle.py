@@ -122,3 +122,25 @@ def test_synchronous_rounds_helper(oracle_mod):
         pins.expect_equal(f, want.f, game.name)
         assert rounds >= 1 and lifts >= changes >= 1
         assert lifts >= int(pins.initially_active_numpy(game).sum())
+
+
+def test_strategy_brute_force(oracle_mod):
+    """Player 0's strategy from the least progress measure wins with exactly the
+    minimum credit (Lemma 1, by brute force) and is the first such edge."""
+    def strat(g, f):
+        choice, missing = oracle_mod.strategy(g, f)
+        assert missing == 0
+        return choice
+    pins.pin_strategy_brute(strat)
+
+
+def test_strategy_cases(oracle_mod):
+    pins.pin_strategy_cases(lambda g, f: oracle_mod.strategy(g, f)[0])
+
+
+def test_strategy_reports_a_non_measure(oracle_mod):
+    """Where f is not a progress measure at a player-0 vertex (every term above
+    f(v)), the vertex gets -1 and is counted."""
+    g = synth.make_game(2, [(0, 1, -3), (1, 1, 0)], [0, 0], W=3)
+    choice, missing = oracle_mod.strategy(g, np.array([1, 0], dtype=np.int64))
+    assert missing == 1 and choice.tolist() == [-1, 0]

@@ -73,5 +73,48 @@ def test_mutant_is_caught(name, tmp_path):
     assert caught is not None, f"no pin detects mutant {name}"
 
 
+# mistakes in the strategy read off the measure (Lemma 1)
+STRATEGY_MUTANTS = {
+    # the last edge that achieves f(v) instead of the first
+    "strategy_last": ("        choice[v] = (int32_t)(e - off[v]);\n        break;",
+                      "        choice[v] = (int32_t)(e - off[v]);"),
+    # only edges strictly below f(v) count
+    "strategy_strict": ("if (term != ORC_TOP && term <= f[v]) {", "if (term != ORC_TOP && term < f[v]) {"),
+    # the global edge index instead of the index within the row
+    "strategy_global": ("choice[v] = (int32_t)(e - off[v]);", "choice[v] = (int32_t)e;"),
+    # player-1 vertices get a choice too
+    "strategy_p1": ("if (owner[v] != 0 || f[v] == ORC_TOP) continue;", "if (f[v] == ORC_TOP) continue;"),
+    # the weight is added instead of subtracted
+    "strategy_sign": ("int64_t term = clamp_to_codomain(ominus(f[tgt[e]], (int64_t)w[e]), bound);",
+                      "int64_t term = clamp_to_codomain(ominus(f[tgt[e]], -(int64_t)w[e]), bound);"),
+}
+
+
+def _strategy_battery(strategy):
+    for name, fn in [("cases", lambda: pins.pin_strategy_cases(strategy)),
+                     ("brute", lambda: pins.pin_strategy_brute(strategy, count=300))]:
+        try:
+            fn()
+        except AssertionError:
+            return name
+    return None
+
+
+@pytest.mark.parametrize("name", sorted(STRATEGY_MUTANTS))
+def test_strategy_mutant_is_caught(name, tmp_path):
+    src = open(oracle.SRC).read()
+    old, new = STRATEGY_MUTANTS[name]
+    assert src.count(old) == 1, f"mutation {name} no longer matches the oracle source"
+    msrc = tmp_path / "mutant.c"
+    msrc.write_text(src.replace(old, new))
+    lib = oracle.build(force=True, src=str(msrc), out=str(tmp_path / f"lib_{name}.so"))
+    caught = _strategy_battery(lambda g, f: oracle.strategy(g, f, lib_path=lib)[0])
+    assert caught is not None, f"no pin detects mutant {name}"
+
+
+def test_unmutated_strategy_passes_battery():
+    assert _strategy_battery(lambda g, f: oracle.strategy(g, f)[0]) is None
+
+
 def test_unmutated_passes_battery():
     assert _battery(lambda g, **kw: oracle.solve(g, **kw).f) is None
