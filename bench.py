@@ -185,6 +185,27 @@ def least_fixpoint(eg, game, stream, shape):
     return f
 
 
+def strategy_timing(g, game, reps=5):
+    """Player 0's strategy read off the least fixpoint (one kernel), against the
+    HBM roofline.  Algorithmic bytes: per vertex its caller-to-internal id, two
+    row starts, f(v) and the choice written (4 + 8 + 8 + 4); per edge scanned up
+    to the first witness, the {target, weight} pair and f(target) (8 + 8)."""
+    import numpy as np
+
+    g.strategy()
+    ts = []
+    for _ in range(reps):
+        choice, t = g.strategy()
+        ts.append(t)
+    t = min(ts)
+    scanned = int(np.sum(choice[choice >= 0].astype(np.int64) + 1))
+    nbytes = game.n * 24.0 + scanned * 16.0
+    gbps = nbytes / t / 1e9
+    log(f"[bench] strategy: {t * 1e6:.1f} us, {scanned} edges scanned, {gbps:.0f} GB/s = {gbps / HBM_PEAK_GBPS:.3f} of peak")
+    return {"us": t * 1e6, "player0_choices": int(np.sum(choice >= 0)), "edges_scanned": scanned,
+            "model_bytes": nbytes, "achieved": gbps, "frac": gbps / HBM_PEAK_GBPS}
+
+
 def rmat_lift_leg(eg, stream, sweeps):
     """Full-frontier lift rounds of the R-MAT scale-22 game: every vertex is
     lifted from the least fixpoint, so nothing changes and the round is the
@@ -212,6 +233,8 @@ def rmat_lift_leg(eg, stream, sweeps):
                     f, st, rc = g.solve(max_rounds=1, resume=True, allow_timeout=True)
                     kt += st["t_round_kernels"]
                     mb += st["model_bytes"]
+                if not over and rc == eg.EG_OK:
+                    res["strategy"] = strategy_timing(g, game)
         us = kt / sweeps * 1e6
         gbps = mb / kt / 1e9
         res[label] = {"us_per_round": us, "model_bytes_per_round": mb / sweeps, "achieved": gbps,

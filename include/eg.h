@@ -190,6 +190,20 @@ int eg_solve_ex(eg_game* g, const eg_solve_opts* opts, int64_t* credits, eg_stat
  * negative or above the bound. */
 int eg_set_measure(eg_game* g, const int64_t* f);
 
+/* Player 0's positional winning strategy (Def. 4 item 2, Def. 5, Lemma 1),
+ * read off the least progress measure that the last eg_solve of g reached.
+ * choice (n entries, caller-owned host memory): for a player-0 vertex v with
+ * finite credit, the index k within v's out-edges (the edge offsets[v] + k of
+ * the caller's arrays) of the first edge (v, u) with f(v) >= f(u) (-) w(v, u);
+ * -1 for player-1 vertices and for vertices of W1 (credit EG_TOP).  Played
+ * from v with initial credit f(v), these edges keep the energy >= 0 against
+ * every player-1 strategy.  t_kernel (nullable) receives the kernel time in
+ * seconds.  EG_EINVAL unless the last eg_solve / eg_solve_ex of g returned
+ * EG_OK with no eg_set_measure since; EG_EDEVICE if some player-0 vertex with
+ * finite credit has no such edge (the measure is not a fixpoint).  Serialised
+ * with the solves of the context. */
+int eg_strategy(eg_game* g, int32_t* choice, double* t_kernel);
+
 /* Serving.  eg_submit copies the game into the context's pending queue and
  * returns at once with a ticket (EG_EBUSY if the queue is full, EG_EINVAL for
  * a malformed game, EG_ENOMEM if the game cannot fit even an empty budget).

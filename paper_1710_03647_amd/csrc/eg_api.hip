@@ -159,6 +159,7 @@ struct eg_game {
   void* perm_mem = nullptr;  // internal id of each caller vertex (renumbered games)
   eg::SeedBuf sb{};
   uint32_t* h_seed = nullptr;
+  bool at_fixpoint = false;  // the device measure is the least fixpoint (last solve returned EG_OK)
 };
 
 // The exported functions keep the C linkage of their declarations in eg.h.
@@ -593,6 +594,7 @@ int eg_set_measure(eg_game* g, const int64_t* f) {
     if (f[v] != EG_TOP && (f[v] < 0 || f[v] > g->bound))
       return fail(EG_EINVAL, "f[%d] = %lld outside [0, %lld] and not EG_TOP", v, (long long)f[v], (long long)g->bound);
   std::lock_guard<std::mutex> lock(g->ctx->solve_mu);
+  g->at_fixpoint = false;
   HIPCHK(hipSetDevice(g->ctx->cfg.device));
   hipStream_t s = g->ctx->stream;
   HIPCHK(hipMemcpyAsync(g->out64, f, 8 * (size_t)g->n, hipMemcpyHostToDevice, s));
@@ -615,6 +617,7 @@ int eg_solve_ex(eg_game* g, const eg_solve_opts* opts, int64_t* credits, eg_stat
   const uint64_t max_rounds = o.max_rounds ? o.max_rounds : ctx->cfg.max_rounds;
   const double budget = o.time_budget_s > 0 ? o.time_budget_s : ctx->cfg.time_budget_s;
   std::lock_guard<std::mutex> lock(ctx->solve_mu);
+  g->at_fixpoint = false;
   HIPCHK(hipSetDevice(ctx->cfg.device));
   hipStream_t s = ctx->stream;
   const eg::DevGame& dg = g->dg;
@@ -785,10 +788,37 @@ int eg_solve_ex(eg_game* g, const eg_solve_opts* opts, int64_t* credits, eg_stat
     st->all_rounds = all_rounds;
   }
   if (status != EG_OK) return fail(status, "budget exhausted after %llu rounds", (unsigned long long)launched);
+  g->at_fixpoint = true;
   return EG_OK;
 }
 
 int eg_solve(eg_game* g, int64_t* credits, eg_stats* st) { return eg_solve_ex(g, nullptr, credits, st); }
+
+int eg_strategy(eg_game* g, int32_t* choice, double* t_kernel) {
+  if (!g || !choice) return fail(EG_EINVAL, "null argument");
+  std::lock_guard<std::mutex> lock(g->ctx->solve_mu);
+  if (!g->at_fixpoint) return fail(EG_EINVAL, "no least fixpoint on the device: eg_solve must return EG_OK first");
+  HIPCHK(hipSetDevice(g->ctx->cfg.device));
+  hipStream_t s = g->ctx->stream;
+  // the output staging buffer (8n bytes) holds the n choices and the counter
+  int32_t* d_choice = (int32_t*)g->out64;
+  uint32_t* d_missing = (uint32_t*)(d_choice + g->n);
+  uint32_t missing = 0;
+  HIPCHK(hipMemsetAsync(d_missing, 0, 4, s));
+  HIPCHK(hipEventRecord(g->ev[0], s));
+  HIPCHK(eg::launch_strategy(g->dg, g->vbits, d_choice, d_missing, s));
+  HIPCHK(hipEventRecord(g->ev[1], s));
+  HIPCHK(hipMemcpyAsync(choice, d_choice, 4 * (size_t)g->n, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&missing, d_missing, 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (t_kernel) {
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, g->ev[0], g->ev[1]);
+    *t_kernel = ms * 1e-3;
+  }
+  if (missing) return fail(EG_EDEVICE, "%u player-0 vertices have no witnessing edge", missing);
+  return EG_OK;
+}
 
 int eg_submit(eg_ctx* ctx, const eg_game_desc* desc, eg_ticket* out) {
   if (!ctx || !desc || !out) return fail(EG_EINVAL, "null argument");

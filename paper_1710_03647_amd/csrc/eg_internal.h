@@ -181,6 +181,9 @@ hipError_t launch_rounds_small(const DevGame& g, int vbits, uint32_t r0, uint32_
 constexpr uint32_t SMALL_LIMIT = 1024;  // active-set size up to which one block runs the rounds
 hipError_t launch_output(const DevGame& g, int vbits, int64_t* out, hipStream_t s);
 hipError_t launch_input(const DevGame& g, int vbits, const int64_t* in, hipStream_t s);
+// Player 0's strategy from the current measure: choice[c] per caller vertex
+// (n entries), missing = player-0 vertices with finite value and no witness.
+hipError_t launch_strategy(const DevGame& g, int vbits, int32_t* choice, uint32_t* missing, hipStream_t s);
 
 int pick_h(double avg_deg);
 int round_grid(int device);

@@ -27,7 +27,7 @@ ERROR_NAMES = {EG_EINVAL: "EG_EINVAL", EG_ENOMEM: "EG_ENOMEM", EG_EDEVICE: "EG_E
                EG_ECANCELED: "EG_ECANCELED", EG_PENDING: "EG_PENDING"}
 
 EXPORTS = ["eg_ctx_create", "eg_ctx_destroy", "eg_check", "eg_create", "eg_destroy", "eg_solve",
-           "eg_solve_ex", "eg_set_measure", "eg_submit", "eg_poll", "eg_cancel", "eg_wait", "eg_solve_batch",
+           "eg_solve_ex", "eg_set_measure", "eg_strategy", "eg_submit", "eg_poll", "eg_cancel", "eg_wait", "eg_solve_batch",
            "eg_last_error"]
 
 
@@ -110,6 +110,7 @@ def lib():
         L.eg_solve.argtypes = [vp, vp, P(eg_stats)]
         L.eg_solve_ex.argtypes = [vp, P(eg_solve_opts), vp, P(eg_stats)]
         L.eg_set_measure.argtypes = [vp, vp]
+        L.eg_strategy.argtypes = [vp, vp, P(ctypes.c_double)]
         L.eg_submit.argtypes = [vp, P(eg_game_desc), P(ctypes.c_uint64)]
         L.eg_poll.argtypes = [vp, ctypes.c_uint64, vp, P(eg_stats)]
         L.eg_cancel.argtypes = [vp, ctypes.c_uint64]
@@ -293,6 +294,18 @@ class Game:
         rc = lib().eg_set_measure(self.handle, _ptr(f))
         if rc != EG_OK:
             raise _err(rc, self.ctx.handle)
+
+    def strategy(self, out=None):
+        """Player 0's positional strategy from the least fixpoint reached by the
+        last solve (eg_strategy).  Returns (choice int32[n], kernel seconds):
+        choice[v] indexes v's out-edges, -1 for player-1 and TOP vertices."""
+        if out is None:
+            out = np.empty(self.n, dtype=np.int32)
+        t = ctypes.c_double(0.0)
+        rc = lib().eg_strategy(self.handle, _ptr(out), ctypes.byref(t))
+        if rc != EG_OK:
+            raise _err(rc, self.ctx.handle)
+        return out, t.value
 
     def destroy(self):
         if self.handle:

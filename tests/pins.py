@@ -325,3 +325,31 @@ def pin_strategy_cases(strategy):
     got = np.asarray(strategy(g, np.array([2, TOP, 0], dtype=np.int64)))
     if got.tolist() != [1, -1, -1]:
         raise AssertionError(f"strategy trap: got {got.tolist()} want [1, -1, -1]")
+
+
+def pin_strategy_properties(game, f, bound, choice, what=""):
+    """Properties of player 0's strategy that hold at any size (numpy, no oracle):
+    -1 exactly on player-1 and TOP vertices; otherwise the chosen edge satisfies
+    the first condition of Def. 5, f(v) >= f(u) (-) w, and no earlier edge does."""
+    f = np.asarray(f, dtype=np.int64)
+    choice = np.asarray(choice, dtype=np.int64)
+    deg = np.diff(game.off).astype(np.int64)
+    want_neg = (game.owner == 1) | (f == TOP)
+    bad = np.nonzero((choice < 0) != want_neg)[0]
+    if len(bad):
+        raise AssertionError(f"{what}: -1 misplaced at {len(bad)} vertices, e.g. {bad[:5]}")
+    if np.any(choice >= deg):
+        raise AssertionError(f"{what}: choice past the end of its row")
+    ft = f[game.tgt.astype(np.int64)]
+    is_top = ft == TOP
+    t = np.where(is_top, TOP, np.maximum(np.where(is_top, 0, ft) - game.w.astype(np.int64), 0))
+    t = np.where((t != TOP) & (t > bound), TOP, t)
+    src = np.repeat(np.arange(game.n), deg)
+    ok = (t != TOP) & (t <= f[src])
+    local = np.arange(len(game.tgt), dtype=np.int64) - game.off[:-1].astype(np.int64)[src]
+    first = np.minimum.reduceat(np.where(ok, local, np.iinfo(np.int64).max), game.off[:-1].astype(np.int64))
+    sel = ~want_neg
+    diff = np.nonzero(first[sel] != choice[sel])[0]
+    if len(diff):
+        v = np.nonzero(sel)[0][diff[:5]]
+        raise AssertionError(f"{what}: choice is not the first witnessing edge at {len(diff)} vertices, e.g. {v}")

@@ -59,3 +59,17 @@ def test_torus_full_budget_is_a_post_fixpoint():
     assert np.all(f <= lifted), "a stop point of the iteration from 0 is below its own lift"
     fin = f[f != TOP]
     assert fin.min() >= 0 and fin.max() <= bound_of(game)
+
+
+@pytest.mark.parametrize("which", ["uniform", "rmat"])
+def test_full_strategy_properties(which):
+    """Player 0's strategy at full size, in the benchmarked launch shape: -1 exactly
+    on player-1 and TOP vertices, else the first edge that witnesses Def. 5."""
+    game = synth.gen_uniform_full() if which == "uniform" else synth.gen_rmat_full()
+    with eg.Context(0, top_seeding=1, **tune.config_for(game)) as c:
+        with c.create(game) as g:
+            f, st, rc = g.solve()
+            choice, t = g.strategy()
+    pins.pin_fixpoint(game, f, bound_of(game), f"{which} seeded")
+    pins.pin_strategy_properties(game, f, bound_of(game), choice, f"{which} strategy")
+    assert t > 0

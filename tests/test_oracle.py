@@ -144,3 +144,20 @@ def test_strategy_reports_a_non_measure(oracle_mod):
     g = synth.make_game(2, [(0, 1, -3), (1, 1, 0)], [0, 0], W=3)
     choice, missing = oracle_mod.strategy(g, np.array([1, 0], dtype=np.int64))
     assert missing == 1 and choice.tolist() == [-1, 0]
+
+
+def test_strategy_properties_helper(oracle_mod):
+    """The numpy property check used at full size accepts the oracle's strategy
+    and rejects a shifted choice."""
+    for g in pins.medium_games():
+        f = oracle_mod.solve(g).f
+        bound = (g.n - 1) * g.W
+        choice, _ = oracle_mod.strategy(g, f)
+        pins.pin_strategy_properties(g, f, bound, choice, g.name)
+        deg = np.diff(g.off)
+        i = np.nonzero((choice >= 0) & (deg > choice + 1))[0]
+        if len(i):
+            bad = choice.copy()
+            bad[i[0]] += 1
+            with pytest.raises(AssertionError):
+                pins.pin_strategy_properties(g, f, bound, bad, g.name)
