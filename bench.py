@@ -258,6 +258,10 @@ def main():
     ap.add_argument("--no-seeded", action="store_true")
     ap.add_argument("--no-rmat-lift", action="store_true")
     ap.add_argument("--rmat-sweeps", type=int, default=10)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 1 GiB on the device three times (scales the FETCH_SIZE/WRITE_SIZE counters)")
+    ap.add_argument("--rmat-only", action="store_true",
+                    help="run only the R-MAT lift and strategy leg and print its JSON (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported; the solver runs on one GPU "
@@ -272,6 +276,19 @@ def main():
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
+    if args.copy_calibration:
+        a = torch.empty(1 << 28, dtype=torch.int32, device=dev)  # 1 GiB
+        b = torch.empty_like(a)
+        a.fill_(1)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print("copied 3 x 1 GiB", flush=True)
+        return
+    if args.rmat_only:
+        print(json.dumps({"rmat_lift": rmat_lift_leg(eg, stream, args.rmat_sweeps)}), flush=True)
+        return
     game, desc = make_game(args.config)
     info = eg.check(game)
     log(f"[bench] {desc}: n={game.n} m={game.m} bound={info['bound']} value_bits={info['value_bits']}")
