@@ -25,7 +25,7 @@ Also reported:
                 log-uniform in [1e3, 1e5], out-degree U{2..16}, W log-uniform in
                 [10, 1000]): one-game-at-a-time solves, the batched server's
                 closed-loop capacity, and Poisson arrivals at 0.8x that capacity
-                with p50/p99 latency (arrival to result).
+                and at 1.2x (overload), with p50/p99 latency (arrival to result).
 
 Flags: --gpus N (only 1 is supported: the solver runs on one GPU),
 --steps K, --warmup W, --config {uniform,plain,rmat,torus}, --no-cpu-baseline,
@@ -34,7 +34,9 @@ fixpoint, every vertex lifted and none changing),
 --max-rounds M (profiling only: stops each solve after M rounds; the line is
 then marked partial), --serve-games G (0 = no serving report), --shape k=v,...
 (launch-shape fields overriding the tuned ones), --no-seeded, --no-rmat-lift,
---rmat-sweeps R (full-frontier rounds timed per R-MAT variant).
+--rmat-sweeps R (full-frontier rounds timed per R-MAT variant); for profiling,
+--rmat-only and --serving-only run one leg and print its JSON, and
+--copy-calibration only copies 1 GiB three times (the counter scale).
 """
 from __future__ import annotations
 
@@ -115,8 +117,27 @@ def cpu_baseline(game, seconds):
                       f"{dt:.1f} s, one thread)"}
 
 
+def poisson_run(ctx, synth, games, rate):
+    """Submit `games` at Poisson arrivals of `rate` games/s; per-game latency
+    (arrival to result) and the wall time until the last result."""
+    arrivals = synth.poisson_arrivals(len(games), rate)
+    t0 = time.perf_counter()
+    tickets = []
+    for g, a in zip(games, arrivals):
+        d = a - (time.perf_counter() - t0)
+        if d > 0:
+            time.sleep(d)
+        tickets.append(ctx.submit(g))
+    lat = []
+    for g, t in zip(games, tickets):
+        rc, f, st = ctx.wait(t, g.n)
+        lat.append(st["t_latency"])
+    return lat, time.perf_counter() - t0
+
+
 def serving_report(eg, synth, count):
-    """One-at-a-time vs batched serving on the first `count` stream games."""
+    """One-at-a-time vs batched serving on the first `count` stream games; Poisson
+    arrivals at 0.8x the batched closed-loop capacity, and an overload run at 1.2x."""
     import numpy as np
 
     games = [synth.gen_stream_game(i) for i in range(count)]
@@ -138,24 +159,18 @@ def serving_report(eg, synth, count):
         cap = count / t_cap
         log(f"[bench] serving: batched closed loop {cap:.2f} games/s ({t_cap:.1f} s)")
         rate = 0.8 * cap
-        arrivals = synth.poisson_arrivals(count, rate)
-        t0 = time.perf_counter()
-        tickets = []
-        for g, a in zip(games, arrivals):
-            d = a - (time.perf_counter() - t0)
-            if d > 0:
-                time.sleep(d)
-            tickets.append(ctx.submit(g))
-        lat = []
-        for g, t in zip(games, tickets):
-            rc, f, st = ctx.wait(t, g.n)
-            lat.append(st["t_latency"])
-        t_poi = time.perf_counter() - t0
+        lat, t_poi = poisson_run(ctx, synth, games, rate)
+        lat_o, t_over = poisson_run(ctx, synth, games, 1.2 * cap)
     res.update({"batched_capacity_games_per_s": cap, "poisson_rate_per_s": rate,
                 "poisson_games_per_s": count / t_poi,
                 "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
+                "overload_rate_per_s": 1.2 * cap, "overload_games_per_s": count / t_over,
+                "overload_p50_latency_s": float(np.percentile(lat_o, 50)),
+                "overload_p99_latency_s": float(np.percentile(lat_o, 99)),
                 "batched_vs_one_at_a_time": cap / (count / t_one)})
     log(f"[bench] serving: Poisson {rate:.2f}/s -> p50 {res['p50_latency_s']:.3f} s, p99 {res['p99_latency_s']:.3f} s")
+    log(f"[bench] serving: overload {1.2 * cap:.2f}/s -> p50 {res['overload_p50_latency_s']:.3f} s, "
+        f"p99 {res['overload_p99_latency_s']:.3f} s")
     return res
 
 
@@ -260,6 +275,8 @@ def main():
     ap.add_argument("--rmat-sweeps", type=int, default=10)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB on the device three times (scales the FETCH_SIZE/WRITE_SIZE counters)")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="run only the serving report and print its JSON")
     ap.add_argument("--rmat-only", action="store_true",
                     help="run only the R-MAT lift and strategy leg and print its JSON (for profiling)")
     args = ap.parse_args()
@@ -285,6 +302,11 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print("copied 3 x 1 GiB", flush=True)
+        return
+    if args.serving_only:
+        from paper_1710_03647_amd import synth as _synth
+
+        print(json.dumps({"serving": serving_report(eg, _synth, args.serve_games)}), flush=True)
         return
     if args.rmat_only:
         print(json.dumps({"rmat_lift": rmat_lift_leg(eg, stream, args.rmat_sweeps)}), flush=True)
