@@ -191,7 +191,9 @@ int eg_solve_ex(eg_game* g, const eg_solve_opts* opts, int64_t* credits, eg_stat
 int eg_set_measure(eg_game* g, const int64_t* f);
 
 /* Player 0's positional winning strategy (Def. 4 item 2, Def. 5, Lemma 1),
- * read off the least progress measure that the last eg_solve of g reached.
+ * read off the least progress measure that the last eg_solve of g reached
+ * (a resumed solve that started above it stops at a larger fixpoint, which
+ * is still a progress measure: the strategy then wins with that credit).
  * choice (n entries, caller-owned host memory): for a player-0 vertex v with
  * finite credit, the index k within v's out-edges (the edge offsets[v] + k of
  * the caller's arrays) of the first edge (v, u) with f(v) >= f(u) (-) w(v, u);
