@@ -29,6 +29,7 @@ Also reported:
 
 Flags: --gpus N (only 1 is supported: the solver runs on one GPU),
 --steps K, --warmup W, --config {uniform,plain,rmat,torus}, --no-cpu-baseline,
+--cpu-seconds S (length of the oracle's bounded sample, default 15),
 --sweep R (instead of solves: R full-frontier lift rounds from the least
 fixpoint, every vertex lifted and none changing),
 --max-rounds M (profiling only: stops each solve after M rounds; the line is

@@ -154,3 +154,21 @@ def test_bench_refuses_more_than_one_gpu():
     r = subprocess.run([sys.executable, eg.os.path.join(eg.os.path.dirname(eg.PKG), "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_bench_flags_are_documented():
+    """Every flag bench.py accepts appears in its --help and in its module docstring."""
+    import re
+    import subprocess
+    import sys
+
+    path = eg.os.path.join(eg.os.path.dirname(eg.PKG), "bench.py")
+    r = subprocess.run([sys.executable, path, "--help"], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0
+    src = open(path).read()
+    doc = src.split('"""')[1]
+    flags = re.findall(r'add_argument\("(--[a-z0-9-]+)"', src)
+    assert len(flags) >= 15
+    for fl in flags:
+        assert fl in r.stdout, fl
+        assert fl in doc, f"{fl} missing from the bench.py docstring"
