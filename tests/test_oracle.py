@@ -161,3 +161,61 @@ def test_strategy_properties_helper(oracle_mod):
             bad[i[0]] += 1
             with pytest.raises(AssertionError):
                 pins.pin_strategy_properties(g, f, bound, bad, g.name)
+
+
+# --------------------------------------------------------------------------- M_G and the unstable count
+def _mg_games():
+    """Hand-computed M_G = sum over v of max(0, max over v's out-edges of -w)
+    (Sec. 3.1): each game lists its edges and the value worked out by hand."""
+    return [
+        # v0: -3, 5 -> 3; v1: 2 -> 0; v2: -1, -7 -> 7; total 10
+        (synth.make_game(3, [(0, 1, -3), (0, 2, 5), (1, 2, 2), (2, 0, -1), (2, 2, -7)], [0, 1, 0], W=7), 10),
+        # every weight non-negative: 0
+        (synth.make_game(2, [(0, 1, 0), (1, 0, 4), (1, 1, 9)], [1, 0], W=0), 0),
+        # duplicates count once per vertex (the worst edge), self-loops count: 6 + 6 + 1
+        (synth.make_game(3, [(0, 0, -6), (0, 0, -6), (1, 2, -6), (1, 2, -2), (2, 2, -1)], [0, 0, 1], W=6), 13),
+        # one vertex, one self-loop of weight -W
+        (synth.make_game(1, [(0, 0, -5)], [1], W=5), 5),
+    ]
+
+
+@pytest.mark.parametrize("k", range(4))
+def test_mg_bound_value_by_hand(oracle_mod, k):
+    g, mg = _mg_games()[k]
+    assert oracle_mod.bound_of(g, oracle_mod.BOUND_MG) == mg
+    assert oracle_mod.solve(g, bound_mode=oracle_mod.BOUND_MG).bound == mg
+
+
+def test_mg_bound_is_tight_on_a_chain(oracle_mod):
+    """Chain v0 -(-3)-> v1 -(-5)-> v2 with a 0 self-loop at v2: M_G = 8 and
+    c(v0) = 8 exactly, so with B = M_G the credit stays finite (a value equal to
+    the bound is kept; one below it would turn v0 into TOP)."""
+    g = synth.make_game(3, [(0, 1, -3), (1, 2, -5), (2, 2, 0)], [0, 1, 0], W=5)
+    assert oracle_mod.bound_of(g, oracle_mod.BOUND_MG) == 8
+    r = oracle_mod.solve(g, bound_mode=oracle_mod.BOUND_MG)
+    pins.expect_equal(r.f, [8, 5, 0], "M_G tight chain")
+    # with an explicit bound one below, v0's credit exceeds it: TOP
+    pins.expect_equal(oracle_mod.solve(g, bound_mode=oracle_mod.BOUND_EXPLICIT, bound=7).f, [TOP, 5, 0],
+                      "bound below the credit")
+
+
+def test_count_unstable_by_hand(oracle_mod):
+    """Independent self-loop vertices: with weight +1 the lift of x is
+    max(0, x - 1), stable only at 0 or TOP; with weight -1 it is x + 1 (TOP
+    above the bound), stable only at TOP; with weight 0 every value is stable.
+    The unstable count of a measure is therefore known vertex by vertex."""
+    ws = [1, 1, 1, -1, -1, 0, 0, 1]
+    g = synth.make_game(len(ws), [(v, v, w) for v, w in enumerate(ws)], [v % 2 for v in range(len(ws))], W=1)
+    B = (g.n - 1) * g.W
+    f = np.array([0, 3, TOP, 0, TOP, 5, TOP, 2], dtype=np.int64)
+    #             ok  bad  ok  bad  ok  ok  ok  bad
+    assert oracle_mod.count_unstable(g, f, B) == 3
+    assert oracle_mod.count_unstable(g, np.zeros(g.n, np.int64), B) == 2  # the two -1 loops
+    # a dependency: v0 -(-2)-> v1, v1 with a 0 self-loop
+    h = synth.make_game(2, [(0, 1, -2), (1, 1, 0)], [0, 0], W=2)
+    assert oracle_mod.count_unstable(h, np.array([0, 0]), 2) == 1
+    assert oracle_mod.count_unstable(h, np.array([2, 0]), 2) == 0
+    assert oracle_mod.count_unstable(h, np.array([2, 5]), 10) == 1
+    # v0's term 1 + 2 = 3 is above B = 2, so its lift is TOP: stable; v1 keeps 1
+    assert oracle_mod.count_unstable(h, np.array([TOP, 1]), 2) == 0
+    assert oracle_mod.count_unstable(h, np.array([TOP, 0]), 2) == 1  # 0 + 2 = 2 = B stays finite
