@@ -65,7 +65,8 @@ typedef uint64_t eg_ticket;
 typedef struct {
   int device;                /* HIP device ordinal */
   void* hip_stream;          /* hipStream_t used by eg_create/eg_solve; NULL = the context's own */
-  uint64_t hbm_budget_bytes; /* serving: device bytes the admitted games may hold; 0 = 80% of free */
+  uint64_t hbm_budget_bytes; /* serving: device bytes the admitted games may hold; 0 = a quarter of the
+                                free device memory (at most the free memory less 1 GiB) */
   int max_slots;             /* serving: games resident at once; 0 = 1024 */
   int bound_mode;            /* EG_BOUND_NW or EG_BOUND_MG */
   uint64_t max_rounds;       /* eg_solve round budget; 0 = none */
@@ -130,6 +131,7 @@ typedef struct {
   uint64_t seeded;        /* vertices set to TOP by seeding passes (top_seeding) */
   uint64_t seed_passes;   /* seeding passes run */
   uint64_t all_rounds;    /* dense rounds that lifted every vertex without activating (frontier ~ V) */
+  double t_seed;          /* eg_solve: device time of the seeding passes (top_seeding), seconds */
 } eg_stats;
 
 /* What eg_check derives from a valid game. */
@@ -157,8 +159,13 @@ typedef struct {
  * when HIP cannot use the device. */
 int eg_ctx_create(const eg_config* cfg, eg_ctx** out);
 
-/* Destroy a context: stops its serving thread, fails in-flight tickets with
- * EG_ECANCELED, frees every game still alive in it. */
+/* Destroy a context.  Every pending or running ticket fails with EG_ECANCELED:
+ * a thread blocked in eg_wait on one returns EG_ECANCELED, and serving calls in
+ * progress on other threads return before the context is freed.  A solve in
+ * progress finishes first.  Then the serving thread stops and every game
+ * created in the context that is still alive is freed (its handle must not be
+ * used afterwards, eg_destroy included).  Calls that start after this one has
+ * returned are undefined: the context no longer exists. */
 int eg_ctx_destroy(eg_ctx* ctx);
 
 /* Validate a game without touching a device (host pointers only).  EG_EINVAL
@@ -172,7 +179,8 @@ int eg_check(const eg_game_desc* desc, int bound_mode, eg_game_info* info, char*
  * stream.  stats (nullable) receives t_upload and t_rcsr. */
 int eg_create(eg_ctx* ctx, const eg_game_desc* desc, eg_game** out, eg_stats* stats);
 
-/* Free a game's device memory. */
+/* Free a game's device memory.  EG_EINVAL for a game that is not alive in its
+ * context. */
 int eg_destroy(eg_game* g);
 
 /* Solve one game to the least fixpoint and copy credits (n entries,
@@ -214,7 +222,11 @@ int eg_strategy(eg_game* g, int32_t* choice, double* t_kernel);
  * batched device iteration; a game that arrives while others run joins them at
  * the next round.  eg_poll returns EG_OK with the credits (n entries) once the
  * game is done (the ticket is then retired), EG_PENDING before, or the
- * ticket's error.  eg_cancel drops a pending or running ticket. */
+ * ticket's error.  eg_cancel drops a pending or running ticket.
+ * eg_submit takes host or device pointers (desc->mem); device arrays are read
+ * on the context's stream, which the call synchronises, and may be freed once
+ * it returns.  After eg_ctx_destroy has started, eg_submit returns
+ * EG_ECANCELED. */
 int eg_submit(eg_ctx* ctx, const eg_game_desc* desc, eg_ticket* out);
 int eg_poll(eg_ctx* ctx, eg_ticket t, int64_t* credits, eg_stats* stats);
 int eg_cancel(eg_ctx* ctx, eg_ticket t);

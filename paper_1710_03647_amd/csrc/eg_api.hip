@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <chrono>
 #include <mutex>
+#include <set>
 #include <string>
 #include <vector>
 
@@ -130,8 +131,11 @@ struct eg_ctx {
   bool own_stream = false;
   int grid = 2048;
   std::mutex solve_mu;
-  std::mutex server_mu;
+  std::mutex server_mu;        // guards server and closing
   eg::Server* server = nullptr;
+  bool closing = false;        // eg_ctx_destroy has started: no new serving thread
+  std::mutex games_mu;
+  std::set<eg_game*> games;    // live games, freed by eg_ctx_destroy
 };
 
 struct eg_game {
@@ -215,12 +219,26 @@ int eg_ctx_create(const eg_config* cfg, eg_ctx** out) {
   return EG_OK;
 }
 
+static void game_free(eg_game* g);
+
 int eg_ctx_destroy(eg_ctx* ctx) {
   if (!ctx) return fail(EG_EINVAL, "null context");
   (void)hipSetDevice(ctx->cfg.device);
-  if (ctx->server) {
-    eg::server_destroy(ctx->server);
+  eg::Server* srv = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(ctx->server_mu);
+    ctx->closing = true;
+    srv = ctx->server;
     ctx->server = nullptr;
+  }
+  // cancels every pending and running ticket, wakes the threads blocked in
+  // eg_wait and waits until every serving call in progress has returned
+  if (srv) eg::server_destroy(srv);
+  {
+    std::lock_guard<std::mutex> solve_lock(ctx->solve_mu);  // a solve in progress finishes first
+    std::lock_guard<std::mutex> lock(ctx->games_mu);
+    for (eg_game* g : ctx->games) game_free(g);
+    ctx->games.clear();
   }
   if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
@@ -242,14 +260,7 @@ static void game_free(eg_game* g) {
   delete g;
 }
 
-// Host copy of a game given by device pointers (for validation).
-struct HostCopy {
-  std::vector<int64_t> off;
-  std::vector<int32_t> tgt, w;
-  std::vector<uint8_t> own;
-};
-
-static int host_view(const eg_game_desc* desc, hipStream_t s, HostCopy& hc, eg_game_desc& hd) {
+int eg::host_view(const eg_game_desc* desc, hipStream_t s, HostCopy& hc, eg_game_desc& hd) {
   hd = *desc;
   if (desc->mem == EG_MEM_HOST) return EG_OK;
   if (desc->mem != EG_MEM_DEVICE) return fail(EG_EINVAL, "unknown memory kind %d", desc->mem);
@@ -417,7 +428,7 @@ static void relabel_by_indegree(const eg_game_desc& d, HostPrep& prep) {
 
 int prepare(const eg_game_desc* desc, int bound_mode, hipStream_t s, HostPrep& prep, std::string* why,
             uint32_t seg_edges, int relabel) {
-  HostCopy hc;
+  eg::HostCopy hc;
   eg_game_desc hd;
   int rc = host_view(desc, s, hc, hd);
   if (rc != EG_OK) {
@@ -577,13 +588,22 @@ int eg_create(eg_ctx* ctx, const eg_game_desc* desc, eg_game** out, eg_stats* st
     (void)hipEventElapsedTime(&ms, g->ev[1], g->ev[2]);
     st->t_rcsr = ms * 1e-3;
   }
+  {
+    std::lock_guard<std::mutex> lock(ctx->games_mu);
+    ctx->games.insert(g);
+  }
   *out = g;
   return EG_OK;
 }
 
 int eg_destroy(eg_game* g) {
   if (!g) return fail(EG_EINVAL, "null game");
-  (void)hipSetDevice(g->ctx->cfg.device);
+  eg_ctx* ctx = g->ctx;
+  (void)hipSetDevice(ctx->cfg.device);
+  {
+    std::lock_guard<std::mutex> lock(ctx->games_mu);
+    if (!ctx->games.erase(g)) return fail(EG_EINVAL, "unknown game");
+  }
   game_free(g);
   return EG_OK;
 }
@@ -646,6 +666,7 @@ int eg_solve_ex(eg_game* g, const eg_solve_opts* opts, int64_t* credits, eg_stat
   if (active && mode != DENSE) HIPCHK(eg::launch_compact(dg, 1, grid, s));
   uint32_t batch = 2;
   double t_kernels = 0;  // device time of the round kernels (back to back within a batch)
+  double t_seed = 0;     // device time of the seeding passes
   uint64_t dense_rounds = 0, all_rounds = 0;
   const bool seeding = ctx->cfg.top_seeding != 0;
   if (seeding && !g->seed_mem) {
@@ -656,9 +677,16 @@ int eg_solve_ex(eg_game* g, const eg_solve_opts* opts, int64_t* credits, eg_stat
   uint64_t next_seed = 0, seeded = 0, seed_passes = 0;  // passes before the first round, then at doubling round counts
   while (active) {
     if (seeding && launched >= next_seed) {
+      HIPCHK(hipEventRecord(g->ev[3], s));
       HIPCHK(eg::launch_seed(dg, g->vbits, g->sb, r, s));
+      HIPCHK(hipEventRecord(g->ev[4], s));
       HIPCHK(hipMemcpyAsync(g->h_seed, g->sb.count, 4, hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
+      {
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, g->ev[3], g->ev[4]);
+        t_seed += ms * 1e-3;
+      }
       seed_passes++;
       next_seed = std::max<uint64_t>(64, 2 * launched);
       if (*g->h_seed) {
@@ -786,6 +814,7 @@ int eg_solve_ex(eg_game* g, const eg_solve_opts* opts, int64_t* credits, eg_stat
     st->seed_passes = seed_passes;
     st->dense_rounds = dense_rounds;
     st->all_rounds = all_rounds;
+    st->t_seed = t_seed;
   }
   if (status != EG_OK) return fail(status, "budget exhausted after %llu rounds", (unsigned long long)launched);
   g->at_fixpoint = true;
@@ -820,25 +849,42 @@ int eg_strategy(eg_game* g, int32_t* choice, double* t_kernel) {
   return EG_OK;
 }
 
+// The context's server with one use taken (released by server_leave), so that
+// eg_ctx_destroy waits for this call before freeing it; nullptr when there is
+// none (and create = false) or the context is being destroyed.
+static eg::Server* server_use(eg_ctx* ctx, bool create) {
+  std::lock_guard<std::mutex> lock(ctx->server_mu);
+  if (ctx->closing) return nullptr;
+  if (!ctx->server && create) ctx->server = eg::server_create(ctx->cfg, ctx->stream);
+  if (ctx->server) eg::server_enter(ctx->server);
+  return ctx->server;
+}
+
 int eg_submit(eg_ctx* ctx, const eg_game_desc* desc, eg_ticket* out) {
   if (!ctx || !desc || !out) return fail(EG_EINVAL, "null argument");
-  {
-    std::lock_guard<std::mutex> lock(ctx->server_mu);
-    if (!ctx->server) ctx->server = eg::server_create(ctx->cfg, ctx->stream);
-  }
-  return eg::server_submit(ctx->server, desc, out);
+  eg::Server* s = server_use(ctx, true);
+  if (!s) return fail(EG_ECANCELED, "the context is being destroyed");
+  const int rc = eg::server_submit(s, desc, ctx->stream, out);
+  eg::server_leave(s);
+  return rc;
 }
 
 int eg_poll(eg_ctx* ctx, eg_ticket t, int64_t* credits, eg_stats* st) {
   if (!ctx) return fail(EG_EINVAL, "null context");
-  if (!ctx->server) return fail(EG_ENOTFOUND, "unknown ticket %llu", (unsigned long long)t);
-  return eg::server_poll(ctx->server, t, credits, st);
+  eg::Server* s = server_use(ctx, false);
+  if (!s) return fail(EG_ENOTFOUND, "unknown ticket %llu", (unsigned long long)t);
+  const int rc = eg::server_poll(s, t, credits, st);
+  eg::server_leave(s);
+  return rc;
 }
 
 int eg_wait(eg_ctx* ctx, eg_ticket t, int64_t* credits, eg_stats* st, double timeout_s) {
   if (!ctx) return fail(EG_EINVAL, "null context");
-  if (!ctx->server) return fail(EG_ENOTFOUND, "unknown ticket %llu", (unsigned long long)t);
-  return eg::server_wait(ctx->server, t, credits, st, timeout_s);
+  eg::Server* s = server_use(ctx, false);
+  if (!s) return fail(EG_ENOTFOUND, "unknown ticket %llu", (unsigned long long)t);
+  const int rc = eg::server_wait(s, t, credits, st, timeout_s);
+  eg::server_leave(s);
+  return rc;
 }
 
 int eg_solve_batch(eg_ctx* ctx, const eg_game_desc* games, int count, int64_t* const* credits, eg_stats* stats) {
@@ -868,6 +914,9 @@ int eg_solve_batch(eg_ctx* ctx, const eg_game_desc* games, int count, int64_t* c
 
 int eg_cancel(eg_ctx* ctx, eg_ticket t) {
   if (!ctx) return fail(EG_EINVAL, "null context");
-  if (!ctx->server) return fail(EG_ENOTFOUND, "unknown ticket %llu", (unsigned long long)t);
-  return eg::server_cancel(ctx->server, t);
+  eg::Server* s = server_use(ctx, false);
+  if (!s) return fail(EG_ENOTFOUND, "unknown ticket %llu", (unsigned long long)t);
+  const int rc = eg::server_cancel(s, t);
+  eg::server_leave(s);
+  return rc;
 }

@@ -149,6 +149,16 @@ struct HostPrep {
 };
 int check_host(const eg_game_desc* d, int bound_mode, eg_game_info* info, std::string* why,
                int64_t* clamp_out, std::vector<uint32_t>* act_bits);
+// Host copy of a game given by device pointers.
+struct HostCopy {
+  std::vector<int64_t> off;
+  std::vector<int32_t> tgt, w;
+  std::vector<uint8_t> own;
+};
+// hd = desc for host descriptors; for device descriptors the arrays are copied
+// into hc on stream s (synchronised) and hd points at them.  EG_OK, EG_EINVAL
+// or EG_EDEVICE (message in the thread's error).
+int host_view(const eg_game_desc* desc, hipStream_t s, HostCopy& hc, eg_game_desc& hd);
 // H2D copy (host descriptor) or device-to-device use (device descriptor), layout,
 // initial-activity flags and predecessor lists into a bound DevGame, on stream s.
 // staging: scratch of staging_bytes(n, m, host) bytes, free once s has completed.

@@ -1191,10 +1191,12 @@ __global__ __launch_bounds__(1024) void k_plan(BatchTable bt) {
   for (uint32_t base = 0; base < bt.nslots; base += 1024) {
     const uint32_t s = base + tid;
     uint32_t tasks = 0;
-    // (relaxed: a slot's game data written in k_batch_small is released before
-    // its mode turns dense, and is read by k_batch_round, a later kernel)
+    // k_batch_small runs beside this kernel on another stream and hands a slot
+    // back by a release store of BM_DENSE after writing the slot's round and
+    // control words; the acquire load orders the reads of those words below
+    // after it (a relaxed load could see the mode and then stale words).
     if (s < bt.nslots && bt.state[s] == SLOT_RUN &&
-        __hip_atomic_load(&bt.mode[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == BM_DENSE) {
+        __hip_atomic_load(&bt.mode[s], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == BM_DENSE) {
       const uint32_t r = bt.round[s];
       const DevGame& g = bt.games[s];
       if (g.ctrl[C_ANY0 + (r - 1) % 3] == 0) {  // round r-1 raised nothing: L_r is empty
@@ -1267,17 +1269,24 @@ __device__ __forceinline__ void batch_task(const BatchTable& bt, RoundShared<V>&
   }
 }
 
+// LDS of a block that runs games of either value width.
+union RoundSharedAny {
+  RoundShared<int32_t> v32;
+  RoundShared<int64_t> v64;
+};
+
 __global__ __launch_bounds__(BLOCK) void k_batch_round(BatchTable bt) {
-  __shared__ RoundShared<int64_t> sh;
+  __shared__ RoundSharedAny sh;
   const uint32_t ntasks = bt.ctl[B_TASKS];
   for (uint32_t x = blockIdx.x; x < ntasks; x += gridDim.x) {
     block_sync();
     const uint32_t s = find_slot(bt.task_begin, bt.nslots, x);
     const uint32_t t = x - bt.task_begin[s];
-    if (bt.games[s].top <= INT32_MAX)  // 32-bit values (see the value width rule)
-      batch_task<int32_t>(bt, reinterpret_cast<RoundShared<int32_t>&>(sh), s, t);
+    // the width the game was laid out with (the rule every launcher follows)
+    if (bt.games[s].vbits == 32)
+      batch_task<int32_t>(bt, sh.v32, s, t);
     else
-      batch_task<int64_t>(bt, sh, s, t);
+      batch_task<int64_t>(bt, sh.v64, s, t);
   }
 }
 
@@ -1328,7 +1337,7 @@ __device__ void batch_small_slot(const BatchTable& bt, RoundShared<V>& sh, uint3
 }
 
 __global__ __launch_bounds__(BLOCK) void k_batch_small(BatchTable bt, uint32_t max_rounds) {
-  __shared__ RoundShared<int64_t> sh;
+  __shared__ RoundSharedAny sh;
   __shared__ uint32_t s_items, s_mode;
   __shared__ int s_changed;
   for (uint32_t s = blockIdx.x; s < bt.nslots; s += gridDim.x) {
@@ -1342,11 +1351,10 @@ __global__ __launch_bounds__(BLOCK) void k_batch_small(BatchTable bt, uint32_t m
     }
     block_sync();
     if (s_mode == BM_DENSE) continue;
-    if (bt.games[s].top <= INT32_MAX)
-      batch_small_slot<int32_t>(bt, reinterpret_cast<RoundShared<int32_t>&>(sh), s, s_mode, max_rounds, s_items,
-                                s_changed);
+    if (bt.games[s].vbits == 32)
+      batch_small_slot<int32_t>(bt, sh.v32, s, s_mode, max_rounds, s_items, s_changed);
     else
-      batch_small_slot<int64_t>(bt, sh, s, s_mode, max_rounds, s_items, s_changed);
+      batch_small_slot<int64_t>(bt, sh.v64, s, s_mode, max_rounds, s_items, s_changed);
   }
 }
 

@@ -148,6 +148,7 @@ struct Server {
   std::unordered_map<eg_ticket, std::unique_ptr<Ticket>> tickets;
   eg_ticket next_id = 1;
   bool stop = false;
+  int users = 0;  // API calls in progress (server_enter .. server_leave)
   bool device_ok = false;
   std::string device_error;
   std::thread worker;
@@ -350,8 +351,8 @@ void Server::retire(int slot, bool finished) {
   nrunning--;
   std::lock_guard<std::mutex> lock(mu);
   t->slot = -1;
-  if (!finished) {
-    t->state = T_CANCELLED;
+  if (!finished || stop) {
+    t->state = T_CANCELLED;  // dropped, or its context is being destroyed
   } else if (e) {
     t->state = T_FAILED;
     t->error = EG_EDEVICE;
@@ -413,7 +414,7 @@ void Server::run() {
       for (int r : outcome) {
         Ticket* t = pending.front();
         pending.pop_front();
-        t->state = r > 0 ? T_RUNNING : T_FAILED;
+        if (t->state != T_CANCELLED) t->state = r > 0 ? T_RUNNING : T_FAILED;
       }
       cv.notify_all();
     }
@@ -497,27 +498,53 @@ Server* server_create(const eg_config& cfg, hipStream_t) {
   return s;
 }
 
+void server_enter(Server* s) {
+  std::lock_guard<std::mutex> lock(s->mu);
+  s->users++;
+}
+
+void server_leave(Server* s) {
+  std::lock_guard<std::mutex> lock(s->mu);
+  if (--s->users == 0) s->cv.notify_all();
+}
+
 void server_destroy(Server* s) {
   if (!s) return;
   {
-    std::lock_guard<std::mutex> lock(s->mu);
+    std::unique_lock<std::mutex> lock(s->mu);
     s->stop = true;
+    // every ticket not yet finished fails with EG_ECANCELED; a thread blocked
+    // in server_wait sees that and returns
+    for (auto& kv : s->tickets) {
+      Ticket* t = kv.second.get();
+      if (t->state == T_PENDING || t->state == T_RUNNING) {
+        t->cancel = true;
+        t->state = T_CANCELLED;
+      }
+    }
+    s->cv.notify_all();
+    s->cv.wait(lock, [&] { return s->users == 0; });
   }
-  s->cv.notify_all();
   if (s->worker.joinable()) s->worker.join();
   s->release_device();
   delete s;
 }
 
-int server_submit(Server* s, const eg_game_desc* desc, eg_ticket* out) {
+int server_submit(Server* s, const eg_game_desc* desc, hipStream_t stream, eg_ticket* out) {
   {
     std::lock_guard<std::mutex> lock(s->mu);
     if (!s->device_ok) return set_err(EG_EDEVICE, s->device_error);
   }
-  if (desc->mem != EG_MEM_HOST) return set_err(EG_EINVAL, "eg_submit takes host pointers");
+  // device-pointer inputs are copied to the host here (the ticket keeps a
+  // host copy of every game until it is admitted)
+  HostCopy hc;
+  eg_game_desc hd;
+  int rc = host_view(desc, stream, hc, hd);
+  if (rc != EG_OK) return rc;
+  desc = &hd;
   auto t = std::make_unique<Ticket>();
   std::string why;
-  int rc = prepare(desc, s->cfg.bound_mode, nullptr, t->prep, &why, 0, 1);
+  rc = prepare(desc, s->cfg.bound_mode, nullptr, t->prep, &why, 0, 1);
   if (rc != EG_OK) return set_err(rc, why);
   t->n = desc->n;
   t->m = desc->m;
@@ -533,6 +560,7 @@ int server_submit(Server* s, const eg_game_desc* desc, eg_ticket* out) {
   t->w.assign(desc->weights, desc->weights + desc->m);
   t->own.assign(desc->owner_bits, desc->owner_bits + ((size_t)desc->n + 7) / 8);
   std::lock_guard<std::mutex> lock(s->mu);
+  if (s->stop) return set_err(EG_ECANCELED, "the context is being destroyed");
   if (s->pending.size() >= s->max_pending) return set_err(EG_EBUSY, "the pending queue is full");
   t->id = s->next_id++;
   t->t_arrive = now_s();

@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import weakref
 from dataclasses import dataclass
 
 import numpy as np
@@ -63,7 +64,7 @@ class eg_stats(ctypes.Structure):
                 ("t_round_kernels", ctypes.c_double), ("t_queue", ctypes.c_double),
                 ("t_latency", ctypes.c_double), ("launched_rounds", ctypes.c_uint64),
                 ("dense_rounds", ctypes.c_uint64), ("seeded", ctypes.c_uint64), ("seed_passes", ctypes.c_uint64),
-                ("all_rounds", ctypes.c_uint64)]
+                ("all_rounds", ctypes.c_uint64), ("t_seed", ctypes.c_double)]
 
     def to_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -200,9 +201,14 @@ class Context:
             raise _err(rc)
         self.handle = p
         self.device = device
+        self._games = weakref.WeakSet()
 
     def close(self):
+        """eg_ctx_destroy: cancels unfinished tickets and frees the context's
+        games (their Game objects are marked destroyed)."""
         if self.handle:
+            for g in list(self._games):
+                g.handle = None
             lib().eg_ctx_destroy(self.handle)
             self.handle = None
 
@@ -219,7 +225,9 @@ class Context:
         rc = lib().eg_create(self.handle, ctypes.byref(desc), ctypes.byref(p), ctypes.byref(st))
         if rc != EG_OK:
             raise _err(rc, self.handle)
-        return Game(self, p, desc.n, st.to_dict())
+        g = Game(self, p, desc.n, st.to_dict())
+        self._games.add(g)
+        return g
 
     # serving
     def submit(self, game=None, **arrays) -> int:

@@ -1,6 +1,7 @@
 """Batched iteration and serving (continuous batching) against the oracle and
 against one-game solves: every game's credits are the same alone and in the
 mix, whatever else shares the device."""
+import threading
 import time
 
 import numpy as np
@@ -13,12 +14,33 @@ pytestmark = pytest.mark.gpu
 GiB = 1 << 30
 
 
+def window_game(n: int, deg: int, seed: int):
+    """A game stored with 64-bit values although the device encoding of TOP
+    (B + P + 1, P the largest positive weight) is below 2^31: W just above
+    2^31 / n and positive weights at most W / 2 put B + P + 1 below 2^31 and
+    B + P + 1 + W above it."""
+    W = (1 << 31) // n + 1
+    g = synth.gen_uniform(n, deg, W, seed, name=f"window-n{n}-s{seed}")
+    w = g.w.astype(np.int64)
+    g.w = np.where(w > W // 2, w // 4, w).astype(np.int32)
+    return g
+
+
+def int64_games():
+    games = [synth.gen_rmat(16, 16, wlim=40000, seed=5), window_game(3, 2, 1), window_game(100, 4, 2),
+             window_game(1000, 4, 3), window_game(5000, 6, 4)]
+    for g in games:
+        info = eg.check(g)
+        assert info["value_bits"] == 64, g.name
+    return games
+
+
 def mix_games():
     games = [synth.gen_stream_game(i, scale_n=0.05) for i in range(10)]
     games += [synth.gen_plain(), synth.gen_torus(16, seed=5), synth.gen_rmat(10, 8, wlim=300, seed=9)]
     games += [synth.gen_random_small(900 + i, n_max=7) for i in range(6)]
     games.append(pins.cf8_game(300))
-    games.append(synth.gen_rmat(12, 16, wlim=40000, seed=5))  # 64-bit values
+    games += int64_games()
     return games
 
 
@@ -125,3 +147,64 @@ def test_small_mode_in_the_batch_counts_every_lift(oracle_mod):
         assert st["changes"] == k + 1 and st["lifts"] == k + 2
     for g, (f, st) in zip(others, res[3:]):
         pins.expect_equal(f, oracle_mod.solve(g).f, g.name)
+
+
+def test_int64_games_in_the_batch_match_oracle(oracle_mod):
+    """Games stored with 64-bit values, including ones whose TOP encoding fits
+    32 bits, run through the epochs and the small mode with their own width."""
+    games = int64_games()
+    with eg.Context(0, hbm_budget_bytes=2 * GiB) as ctx:
+        res = ctx.solve_batch(games)
+    for g, (f, st) in zip(games, res):
+        pins.expect_equal(f, oracle_mod.solve(g).f, g.name)
+
+
+def test_destroy_context_cancels_tickets_and_wakes_waiter():
+    """eg_ctx_destroy while a thread is blocked in eg_wait on a running game:
+    the waiter returns EG_ECANCELED, the pending ticket is cancelled too, and
+    the context's live game is freed with it."""
+    slow = synth.gen_torus(128, seed=4)  # many seconds of rounds: still running when the context goes
+    ctx = eg.Context(0, hbm_budget_bytes=GiB, max_slots=1)
+    live = ctx.create(synth.gen_plain())
+    t_run = ctx.submit(slow)
+    t_wait = ctx.submit(slow)  # no free slot: stays pending
+    got = {}
+
+    def waiter(name, t):
+        try:
+            ctx_handle_wait = ctx.wait(t, slow.n)
+            got[name] = ("returned", ctx_handle_wait[0])
+        except eg.EgError as e:
+            got[name] = ("error", e.code)
+
+    threads = [threading.Thread(target=waiter, args=("running", t_run)),
+               threading.Thread(target=waiter, args=("pending", t_wait))]
+    for th in threads:
+        th.start()
+    time.sleep(0.5)
+    assert not got, "the slow game finished before the context was destroyed"
+    ctx.close()
+    for th in threads:
+        th.join(timeout=60)
+        assert not th.is_alive()
+    assert got == {"running": ("error", eg.EG_ECANCELED), "pending": ("error", eg.EG_ECANCELED)}
+    assert live.handle is None
+    live.destroy()  # a no-op once the context has freed it
+
+
+def test_submit_device_pointers(oracle_mod):
+    import torch
+
+    dev = torch.device("cuda", 0)
+    games = [synth.gen_stream_game(i, scale_n=0.05) for i in range(3)]
+    with eg.Context(0, hbm_budget_bytes=GiB) as ctx:
+        tickets = []
+        for game in games:
+            arrs = [torch.from_numpy(a).to(dev) for a in (game.off, game.tgt, game.w, game.owner_bits())]
+            torch.cuda.synchronize()
+            tickets.append(ctx.submit(n=game.n, offsets=arrs[0], targets=arrs[1], weights=arrs[2],
+                                      owner_bits=arrs[3], W=game.W, device=True))
+            del arrs  # the call copied them
+        for game, t in zip(games, tickets):
+            rc, f, st = ctx.wait(t, game.n)
+            pins.expect_equal(f, oracle_mod.solve(game).f, f"{game.name}: device-pointer submit")
