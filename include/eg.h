@@ -79,9 +79,12 @@ typedef struct {
   int blocks_per_cu;         /* resident blocks of 256 threads per compute unit in round kernels: 8 */
   int dense_div;             /* flag sweeps while the active set holds >= n / dense_div vertices: 32 */
   int small_limit;           /* one block runs the rounds while the active set holds <= this: 1024 */
-  int top_seeding;           /* eg_solve: 1 = set TOP on the vertices of negative cycles that player 1
-                                can force (found between rounds, before the first one and at doubling
-                                round counts); exact, the credits do not change, only the work */
+  int top_seeding;           /* 1 = set TOP on the vertices of negative cycles that player 1 can force
+                                (Lemma 1): eg_solve runs such a pass before the first round and again
+                                at doubling round counts; serving (eg_submit, eg_solve_batch) runs one
+                                before each game's first round (its device footprint then includes
+                                34 bytes per vertex of scratch).  Exact: the credits do not change,
+                                only the work */
   int seg_edges;             /* launch shape: dense rounds cut a tile of 256 vertices whose out-degrees
                                 sum above this into segments taken by different blocks: 8192
                                 (0 = default, -1 = never cut; else >= 256) */
@@ -192,6 +195,24 @@ int eg_solve(eg_game* g, int64_t* credits, eg_stats* stats);
 
 /* eg_solve with per-call options (NULL opts = eg_solve). */
 int eg_solve_ex(eg_game* g, const eg_solve_opts* opts, int64_t* credits, eg_stats* stats);
+
+/* For callers that cannot allocate device memory during a solve (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * eg_solve_ex with TOP seeding on (whatever the context's top_seeding says),
+ * whose seeding scratch is a static device array of the library instead of
+ * memory allocated by the first seeded solve.  The call allocates nothing
+ * (no hipMalloc, hipFree or allocating library routine); the game, its
+ * buffers and the pinned host words it uses were allocated by eg_create.  The
+ * array holds the scratch of games up to EG_NOALLOC_MAX_N vertices (34 bytes
+ * per vertex, 136 MiB in all); each device holds its own copy from its first
+ * such call until the process ends.  Every call on one device uses that
+ * device's copy, so calls on one device are serialised (a call waits while
+ * another, from any context, runs); every scratch word a pass reads is written
+ * by that pass first, so no state carries over between calls.  EG_EINVAL
+ * when g has more than EG_NOALLOC_MAX_N vertices; otherwise as eg_solve_ex,
+ * with the same credits. */
+#define EG_NOALLOC_MAX_N (1 << 22)
+int eg_solve_seeded_noalloc(eg_game* g, const eg_solve_opts* opts, int64_t* credits, eg_stats* stats);
 
 /* Replace the game's current measure (n entries, host memory, EG_TOP allowed)
  * before an eg_solve_ex with resume = 1.  EG_EINVAL if a finite value is

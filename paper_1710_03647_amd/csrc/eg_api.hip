@@ -518,6 +518,8 @@ int eg_create(eg_ctx* ctx, const eg_game_desc* desc, eg_game** out, eg_stats* st
     return cleanup_fail(EG_EDEVICE, "hipHostMalloc", e);
   if ((e = hipHostMalloc((void**)&g->h_blk, 4 * nblk, hipHostMallocDefault)) != hipSuccess)
     return cleanup_fail(EG_EDEVICE, "hipHostMalloc", e);
+  if ((e = hipHostMalloc((void**)&g->h_seed, 4, hipHostMallocDefault)) != hipSuccess)
+    return cleanup_fail(EG_EDEVICE, "hipHostMalloc", e);
   for (auto& ev : g->ev)
     if ((e = hipEventCreate(&ev)) != hipSuccess) return cleanup_fail(EG_EDEVICE, "hipEventCreate", e);
 
@@ -628,7 +630,11 @@ int eg_set_measure(eg_game* g, const int64_t* f) {
 // fixpoint (an empty active set) and to choose the representation of the next
 // batch: dense while the active set is a large fraction of V, sparse (a list)
 // otherwise.  Extra rounds enqueued after the fixpoint find no work and return.
-int eg_solve_ex(eg_game* g, const eg_solve_opts* opts, int64_t* credits, eg_stats* st) {
+// fixed_sb: seeding scratch supplied by the caller (seeding is then on
+// whatever the context says); nullptr: the game's own, allocated by its first
+// seeded solve.
+static int solve_impl(eg_game* g, const eg_solve_opts* opts, int64_t* credits, eg_stats* st,
+                      const eg::SeedBuf* fixed_sb) {
   if (!g) return fail(EG_EINVAL, "null game");
   eg_solve_opts o{};
   if (opts) o = *opts;
@@ -668,10 +674,11 @@ int eg_solve_ex(eg_game* g, const eg_solve_opts* opts, int64_t* credits, eg_stat
   double t_kernels = 0;  // device time of the round kernels (back to back within a batch)
   double t_seed = 0;     // device time of the seeding passes
   uint64_t dense_rounds = 0, all_rounds = 0;
-  const bool seeding = ctx->cfg.top_seeding != 0;
-  if (seeding && !g->seed_mem) {
-    HIPCHK(hipMalloc(&g->seed_mem, eg::seed_bytes(g->n)));
-    HIPCHK(hipHostMalloc((void**)&g->h_seed, 4, hipHostMallocDefault));
+  const bool seeding = fixed_sb || ctx->cfg.top_seeding != 0;
+  if (fixed_sb) {
+    g->sb = *fixed_sb;
+  } else if (seeding) {
+    if (!g->seed_mem) HIPCHK(hipMalloc(&g->seed_mem, eg::seed_bytes(g->n)));
     eg::bind_seed(g->sb, g->seed_mem, g->n);
   }
   uint64_t next_seed = 0, seeded = 0, seed_passes = 0;  // passes before the first round, then at doubling round counts
@@ -821,7 +828,64 @@ int eg_solve_ex(eg_game* g, const eg_solve_opts* opts, int64_t* credits, eg_stat
   return EG_OK;
 }
 
+int eg_solve_ex(eg_game* g, const eg_solve_opts* opts, int64_t* credits, eg_stats* st) {
+  return solve_impl(g, opts, credits, st, nullptr);
+}
+
 int eg_solve(eg_game* g, int64_t* credits, eg_stats* st) { return eg_solve_ex(g, nullptr, credits, st); }
+
+// ---------------------------------------------------------------- seeded solve without allocation
+//
+// The seeding scratch of eg_solve_seeded_noalloc: one array per device, which
+// each device holds from the first such call until the process ends.  In host
+// code `scratch` names a host-side stand-in; the device address of a device's
+// copy comes from hipGetSymbolAddress, taken once per device on its first
+// call (not at context creation, so that processes that never make this call
+// do not load and hold the array).
+namespace {
+constexpr size_t pad256(size_t x) { return (x + 255) & ~(size_t)255; }
+// the layout of eg::seed_bytes for EG_NOALLOC_MAX_N vertices
+constexpr size_t NOALLOC_SCRATCH_BYTES = 6 * pad256(4 * (size_t)EG_NOALLOC_MAX_N) +
+                                         2 * pad256((size_t)EG_NOALLOC_MAX_N) + pad256(8 * (size_t)EG_NOALLOC_MAX_N) +
+                                         pad256(4);
+__device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+constexpr int NOALLOC_DEVICES = 64;
+std::mutex scratch_table_mu;
+void* scratch_ptr[NOALLOC_DEVICES];           // device address of each device's copy (nullptr: not taken yet)
+std::mutex scratch_use_mu[NOALLOC_DEVICES];   // one call at a time per device uses its copy
+
+int noalloc_scratch(int device, void** out) {
+  if (device < 0 || device >= NOALLOC_DEVICES) return fail(EG_EDEVICE, "device %d beyond the scratch table", device);
+  std::lock_guard<std::mutex> lock(scratch_table_mu);
+  if (!scratch_ptr[device]) {
+    HIPCHK(hipSetDevice(device));
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return fail(EG_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    scratch_ptr[device] = p;
+  }
+  *out = scratch_ptr[device];
+  return EG_OK;
+}
+}  // namespace
+
+int eg_solve_seeded_noalloc(eg_game* g, const eg_solve_opts* opts, int64_t* credits, eg_stats* st) {
+  if (!g) return fail(EG_EINVAL, "null game");
+  if (g->n > EG_NOALLOC_MAX_N)
+    return fail(EG_EINVAL, "n = %d exceeds EG_NOALLOC_MAX_N = %d, the vertices the static seeding scratch holds",
+                g->n, EG_NOALLOC_MAX_N);
+  static_assert(NOALLOC_SCRATCH_BYTES >= 34 * (size_t)EG_NOALLOC_MAX_N, "scratch smaller than seed_bytes");
+  const int device = g->ctx->cfg.device;
+  void* base = nullptr;
+  const int rc = noalloc_scratch(device, &base);
+  if (rc != EG_OK) return rc;
+  if (eg::seed_bytes(g->n) > NOALLOC_SCRATCH_BYTES) return fail(EG_EINVAL, "seeding scratch layout too large");
+  // calls on one device share its copy: they run one after another
+  std::lock_guard<std::mutex> lock(scratch_use_mu[device]);
+  eg::SeedBuf sb{};
+  eg::bind_seed(sb, base, g->n);
+  return solve_impl(g, opts, credits, st, &sb);
+}
 
 int eg_strategy(eg_game* g, int32_t* choice, double* t_kernel) {
   if (!g || !choice) return fail(EG_EINVAL, "null argument");

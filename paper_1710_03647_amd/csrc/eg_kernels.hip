@@ -334,6 +334,14 @@ __device__ __forceinline__ uint32_t find_range(const uint32_t* pre, uint32_t x) 
   return lo;
 }
 
+// Terms of one chunk of UNROLL * BLOCK edges in the contiguous-row lift: the
+// term of chunk position q sits at (q % UNROLL) * (BLOCK + 1) + q / UNROLL, so
+// that the fold (thread t reads positions t * UNROLL + j) and the stream (lane
+// i writes positions j * BLOCK + i) both touch consecutive words per lane
+// group; the pad word per row staggers the banks of the groups.
+constexpr int TERM_ROW = BLOCK + 1;
+__device__ __forceinline__ uint32_t term_slot(uint32_t q) { return (q % UNROLL) * TERM_ROW + q / UNROLL; }
+
 template <typename V>
 struct RoundShared {
   uint32_t epre[BLOCK + 1];  // exclusive prefix of out-degrees of the tile's active vertices
@@ -343,10 +351,18 @@ struct RoundShared {
   uint32_t pbeg[BLOCK];      // their predecessor-list starts
   uint32_t wsum[BLOCK / WAVE];
   uint32_t wbig[BLOCK / WAVE];  // per wave: some active vertex has more than LANE_DEG out-edges
-  int32_t push[PUSH_CAP];    // sparse: staged entries of L_{r+1}
+  // push stages list entries across the tiles of a sparse round; term is used
+  // only by the contiguous-row lift, which only dense and all-vertex rounds
+  // take, and those never stage entries
+  union {
+    int32_t push[PUSH_CAP];      // sparse: staged entries of L_{r+1}
+    V term[UNROLL * TERM_ROW];   // contiguous-row lift: the terms of one chunk
+  };
   unsigned long long st[S_WORDS];
   uint32_t n_push, base;
+  uint32_t cbase;  // contiguous-row lift: first edge of the tile's rows, or NO_CONTIG
 };
+constexpr uint32_t NO_CONTIG = 0xFFFFFFFFu;
 
 // Reads of data used once per round (plain loads measured faster than
 // non-temporal ones on gfx950 here).
@@ -429,6 +445,93 @@ __device__ __forceinline__ void lift_edges(const DevGame& g, RoundShared<V>& sh,
     if (sl < BLOCK && (lane == 0 || sprev != sl))
       __hip_atomic_fetch_min(&sh.key[sl], k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   }
+}
+
+// Edges [x0, min(x0 + J * BLOCK, E)) of a tile whose active rows are one
+// contiguous run of edges from `base` (every vertex of the tile active): the
+// edge of position x is edges[base + x], so no search is needed to load it.
+// The block streams the chunk coalesced (lane i takes positions j * BLOCK + i),
+// gathers f of every target with J gathers in flight per lane, and writes the
+// unsigned terms max(0, f(u) - w) to LDS.  Then thread t folds the contiguous
+// positions [t * J, t * J + J): one search finds the vertex of its first
+// edge, the thread walks forward across row boundaries, keeps the running key
+// of the current vertex in a register and folds it into the vertex's LDS key
+// (one atomic min per vertex and thread) when the row or the run ends.  Ends
+// with a barrier: the next chunk rewrites the terms.
+template <typename V, int J>
+__device__ __forceinline__ void lift_contig(const DevGame& g, RoundShared<V>& sh, const V* f, uint32_t base,
+                                            uint32_t x0, uint32_t E) {
+  static_assert(J <= UNROLL, "a chunk holds at most UNROLL * BLOCK terms");
+  const uint32_t tid = threadIdx.x;
+  int2 ed[J];
+#pragma unroll
+  for (int j = 0; j < J; j++) {
+    const uint32_t x = x0 + j * BLOCK + tid;
+    ed[j] = load_edge(g.edges, base + (x < E ? x : E - 1));
+  }
+  V fu[J];
+#pragma unroll
+  for (int j = 0; j < J; j++) fu[j] = f[ed[j].x];
+#pragma unroll
+  for (int j = 0; j < J; j++) {
+    V tm = fu[j] - (V)ed[j].y;
+    sh.term[term_slot(j * BLOCK + tid)] = tm > V(0) ? tm : V(0);
+  }
+  block_sync();
+  const uint32_t a = x0 + tid * UNROLL;  // this thread's positions [a, a + UNROLL) of the chunk
+  if (a < E && tid * UNROLL < (uint32_t)J * BLOCK) {
+    uint32_t sl = find_range(sh.epre, a);
+    uint32_t next = sh.epre[sl + 1];
+    bool neg = (sh.ebeg[sl] & OWNER_BIT) != 0;
+    V acc = std::numeric_limits<V>::max();
+#pragma unroll
+    for (int j = 0; j < UNROLL; j++) {
+      const uint32_t x = a + j;
+      if (x < E) {
+        if (x >= next) {  // a row ends inside the run: its vertices have degree >= 1
+          __hip_atomic_fetch_min(&sh.key[sl], acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          do {
+            sl++;
+            next = sh.epre[sl + 1];
+          } while (x >= next);
+          neg = (sh.ebeg[sl] & OWNER_BIT) != 0;
+          acc = std::numeric_limits<V>::max();
+        }
+        const V tm = sh.term[j * TERM_ROW + tid];
+        const V k = neg ? -tm : tm;
+        acc = k < acc ? k : acc;
+      }
+    }
+    __hip_atomic_fetch_min(&sh.key[sl], acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+  block_sync();
+}
+
+static_assert(UNROLL == 4, "lift_contig_range dispatches chunk widths 1 to 4");
+
+// Positions [lo, hi) of a contiguous tile, chunk by chunk (block-uniform).
+template <typename V>
+__device__ __forceinline__ void lift_contig_range(const DevGame& g, RoundShared<V>& sh, const V* f, uint32_t base,
+                                                  uint32_t lo, uint32_t hi) {
+  for (uint32_t x0 = lo; x0 < hi; x0 += BLOCK * UNROLL) {
+    switch (std::min<uint32_t>((hi - x0 + BLOCK - 1) / BLOCK, UNROLL)) {
+      case 1: lift_contig<V, 1>(g, sh, f, base, x0, hi); break;
+      case 2: lift_contig<V, 2>(g, sh, f, base, x0, hi); break;
+      case 3: lift_contig<V, 3>(g, sh, f, base, x0, hi); break;
+      default: lift_contig<V, UNROLL>(g, sh, f, base, x0, hi); break;
+    }
+  }
+}
+
+// First edge of the rows of vertex tile t when the active set of a dense round
+// holds every vertex of the tile (E out-edges in all: every vertex has at
+// least one, so E equals the span of the tile's rows exactly then), else
+// NO_CONTIG.
+__device__ __forceinline__ uint32_t contig_base(const DevGame& g, uint32_t t, uint32_t E) {
+  const uint32_t first = t * TILE;
+  const uint32_t last1 = min((uint32_t)g.n, first + TILE);
+  const uint32_t b = g.rs[first] & ROW_MASK;
+  return (g.rs[last1] & ROW_MASK) - b == E ? b : NO_CONTIG;
 }
 
 // Predecessor entries [x0, x0 + J * BLOCK) of the tile's changed vertices,
@@ -608,6 +711,7 @@ __device__ __forceinline__ void round_tile(const DevGame& g, RoundShared<V>& sh,
   if (tid == BLOCK - 1) sh.epre[BLOCK] = E;
   sh.ebeg[tid] = raw;
   sh.key[tid] = (raw & OWNER_BIT) ? V(0) : std::numeric_limits<V>::max();
+  if ((DENSE || ALL) && !PART && tid == 0) sh.cbase = contig_base(g, t, E);
   if (PART && v >= 0) {
     // the slices' partial keys of v, computed by k_partial
     V k = sh.key[tid];
@@ -623,6 +727,8 @@ __device__ __forceinline__ void round_tile(const DevGame& g, RoundShared<V>& sh,
 
   if (!PART && lanes) {
     sh.key[tid] = lift_lanes<V>(g, f, v, raw, deg);
+  } else if (!PART && (DENSE || ALL) && sh.cbase != NO_CONTIG) {
+    lift_contig_range<V>(g, sh, f, sh.cbase, 0, E);
   } else if (!PART) {
     for (uint32_t x0 = 0; x0 < E; x0 += BLOCK * UNROLL) {
       switch (std::min<uint32_t>((E - x0 + BLOCK - 1) / BLOCK, UNROLL)) {
@@ -747,11 +853,14 @@ __device__ __forceinline__ void round_seg(const DevGame& g, RoundShared<V>& sh, 
   sh.ebeg[tid] = raw;
   const V ident = (raw & OWNER_BIT) ? V(0) : std::numeric_limits<V>::max();
   sh.key[tid] = ident;
+  if (tid == 0) sh.cbase = contig_base(g, t, E);
   block_sync();
   if (E == 0) return;  // block-uniform, and the same in every segment block of the tile
   const uint32_t lo = (uint32_t)((uint64_t)E * seg / nseg), hi = (uint32_t)((uint64_t)E * (seg + 1) / nseg);
+  const bool contig = !lanes && sh.cbase != NO_CONTIG;
   if (lanes) sh.key[tid] = lift_lanes<V>(g, f, v, raw, deg);
-  for (uint32_t x0 = lo; x0 < (lanes ? lo : hi); x0 += BLOCK * UNROLL) {
+  if (contig) lift_contig_range<V>(g, sh, f, sh.cbase, lo, hi);
+  for (uint32_t x0 = lo; x0 < (lanes || contig ? lo : hi); x0 += BLOCK * UNROLL) {
     switch (std::min<uint32_t>((hi - x0 + BLOCK - 1) / BLOCK, UNROLL)) {
       case 1: lift_edges<V, 1>(g, sh, f, x0, hi); break;
       case 2: lift_edges<V, 2>(g, sh, f, x0, hi); break;
@@ -1057,36 +1166,137 @@ __global__ void k_seed_forced(DevGame g, SeedBuf sb) {
   }
 }
 
+// Rows of player-1 vertices up to this length are scanned by their own lane;
+// longer ones by the whole wave, SEED_UNROLL * 64 edges per step, so that a hub
+// costs deg / 256 dependent steps instead of deg.
+constexpr uint32_t SEED_SHORT = 32;
+constexpr int SEED_UNROLL = 4;
+
+// Candidate order of sigma1: a negative self-loop first (player 1 can stay on
+// it forever, so it is always a certificate), then the largest term, then the
+// lowest edge index.  Returns true when (lb, tb, kb) beats (la, ta, ka).
 template <typename V>
-__global__ void k_seed_choose(DevGame g, SeedBuf sb) {
+__device__ __forceinline__ bool seed_better(bool lb, V tb, uint32_t kb, bool la, V ta, uint32_t ka) {
+  if (lb != la) return lb;
+  if (tb != ta) return tb > ta;
+  return kb < ka;
+}
+
+// sigma1 for every player-1 vertex over its out-edges into the forced subgraph;
+// the single edge of every player-0 vertex of out-degree 1.
+template <typename V>
+__global__ __launch_bounds__(BLOCK) void k_seed_choose(DevGame g, SeedBuf sb) {
   const V* f = (const V*)g.f;
-  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < (uint32_t)g.n; v += gridDim.x * blockDim.x) {
-    const uint32_t a = g.rs[v], e0 = a & ROW_MASK, e1 = g.rs[v + 1] & ROW_MASK;
-    int32_t best = -1, bw = 0;
-    if (a & OWNER_BIT) {
-      V bt = -1;
-      for (uint32_t e = e0; e < e1; e++) {
-        const int2 ed = g.edges[e];
-        if (!sb.forced[ed.x]) continue;
-        V tm = f[ed.x] - (V)ed.y;
-        tm = tm > V(0) ? tm : V(0);
-        if (tm > bt) {
-          bt = tm;
-          best = ed.x;
-          bw = ed.y;
+  const uint32_t n = (uint32_t)g.n;
+  const uint32_t lane = lane_id();
+  const uint32_t stride = gridDim.x * blockDim.x;
+  constexpr uint32_t NONE = 0xFFFFFFFFu;
+  // v0 is the wave's first vertex: the same in every lane, so ballots see the whole wave
+  for (uint32_t v0 = blockIdx.x * blockDim.x + threadIdx.x - lane; v0 < n; v0 += stride) {
+    const uint32_t v = v0 + lane;
+    uint32_t e0 = 0, deg = 0;
+    bool p1 = false;
+    if (v < n) {
+      const uint32_t a = g.rs[v];
+      e0 = a & ROW_MASK;
+      deg = (g.rs[v + 1] & ROW_MASK) - e0;
+      p1 = (a & OWNER_BIT) != 0;
+    }
+    uint32_t kbest = NONE;
+    if (v < n && p1 && deg <= SEED_SHORT) {
+      bool lbest = false;
+      V tbest = -1;
+      for (uint32_t k0 = 0; k0 < deg; k0 += SEED_UNROLL) {
+        int2 ed[SEED_UNROLL];
+#pragma unroll
+        for (int j = 0; j < SEED_UNROLL; j++) ed[j] = g.edges[e0 + min(k0 + j, deg - 1)];
+        uint8_t fz[SEED_UNROLL];
+        V fu[SEED_UNROLL];
+#pragma unroll
+        for (int j = 0; j < SEED_UNROLL; j++) {
+          fz[j] = sb.forced[ed[j].x];
+          fu[j] = f[ed[j].x];
+        }
+#pragma unroll
+        for (int j = 0; j < SEED_UNROLL; j++) {
+          const uint32_t k = k0 + j;
+          if (k >= deg || !fz[j]) continue;
+          const bool l = ed[j].x == (int32_t)v && ed[j].y < 0;
+          V tm = fu[j] - (V)ed[j].y;
+          tm = tm > V(0) ? tm : V(0);
+          if (kbest == NONE || seed_better<V>(l, tm, k, lbest, tbest, kbest)) {
+            lbest = l;
+            tbest = tm;
+            kbest = k;
+          }
         }
       }
-    } else if (e1 - e0 == 1) {
-      const int2 ed = g.edges[e0];
-      best = ed.x;
-      bw = ed.y;
+    } else if (v < n && !p1 && deg == 1) {
+      kbest = 0;
     }
-    sb.succ[v] = best;
-    sb.wgt[v] = bw;
-    sb.p[0][v] = best;
-    sb.lo[0][v] = (int32_t)v;
-    sb.oncyc[v] = 0;
-    sb.sum[v] = 0;
+    unsigned long long longs = __ballot(v < n && p1 && deg > SEED_SHORT);
+    while (longs) {
+      const uint32_t src = (uint32_t)__ffsll((long long)longs) - 1;
+      longs &= longs - 1;
+      const uint32_t b = __shfl(e0, (int)src, WAVE);
+      const uint32_t d = __shfl(deg, (int)src, WAVE);
+      const int32_t vv = (int32_t)(v0 + src);
+      bool l = false;
+      V t = -1;
+      uint32_t kk = NONE;
+      for (uint32_t k0 = 0; k0 < d; k0 += SEED_UNROLL * WAVE) {
+        int2 ed[SEED_UNROLL];
+#pragma unroll
+        for (int j = 0; j < SEED_UNROLL; j++) ed[j] = g.edges[b + min(k0 + j * WAVE + lane, d - 1)];
+        uint8_t fz[SEED_UNROLL];
+        V fu[SEED_UNROLL];
+#pragma unroll
+        for (int j = 0; j < SEED_UNROLL; j++) {
+          fz[j] = sb.forced[ed[j].x];
+          fu[j] = f[ed[j].x];
+        }
+#pragma unroll
+        for (int j = 0; j < SEED_UNROLL; j++) {
+          const uint32_t k = k0 + j * WAVE + lane;
+          if (k >= d || !fz[j]) continue;
+          const bool lj = ed[j].x == vv && ed[j].y < 0;
+          V tm = fu[j] - (V)ed[j].y;
+          tm = tm > V(0) ? tm : V(0);
+          if (kk == NONE || seed_better<V>(lj, tm, k, l, t, kk)) {
+            l = lj;
+            t = tm;
+            kk = k;
+          }
+        }
+      }
+      // the wave's best candidate (NONE loses to every candidate)
+#pragma unroll
+      for (int o = 1; o < WAVE; o <<= 1) {
+        const bool lo_ = __shfl_xor((int)l, o, WAVE) != 0;
+        const V to = __shfl_xor(t, o, WAVE);
+        const uint32_t ko = __shfl_xor(kk, o, WAVE);
+        if (ko != NONE && (kk == NONE || seed_better<V>(lo_, to, ko, l, t, kk))) {
+          l = lo_;
+          t = to;
+          kk = ko;
+        }
+      }
+      if (lane == src) kbest = kk;
+    }
+    if (v < n) {
+      int32_t best = -1, bw = 0;
+      if (kbest != NONE) {
+        const int2 ed = g.edges[e0 + kbest];
+        best = ed.x;
+        bw = ed.y;
+      }
+      sb.succ[v] = best;
+      sb.wgt[v] = bw;
+      sb.p[0][v] = best;
+      sb.lo[0][v] = (int32_t)v;
+      sb.oncyc[v] = 0;
+      sb.sum[v] = 0;
+    }
   }
 }
 
@@ -1109,17 +1319,36 @@ __global__ void k_seed_sum(int32_t n, const SeedBuf sb, const int32_t* lo) {
 }
 
 // TOP on the vertices of negative cycles; their predecessors join L_r (flags).
+// A short predecessor list is flagged by its lane, a long one by the whole wave.
 template <typename V>
-__global__ void k_seed_apply(DevGame g, const SeedBuf sb, const int32_t* lo, uint32_t r) {
+__global__ __launch_bounds__(BLOCK) void k_seed_apply(DevGame g, const SeedBuf sb, const int32_t* lo, uint32_t r) {
   V* f = (V*)g.f;
   const V top = (V)g.top;
   uint8_t* act = (r & 1) ? g.act1 : g.act0;
+  const uint32_t n = (uint32_t)g.n;
+  const uint32_t lane = lane_id();
+  const uint32_t stride = gridDim.x * blockDim.x;
   uint32_t mine = 0;
-  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < (uint32_t)g.n; v += gridDim.x * blockDim.x) {
-    if (!sb.oncyc[v] || sb.sum[lo[v]] >= 0 || f[v] == top) continue;
-    f[v] = top;
-    mine++;
-    for (uint32_t k = g.rev_off[v]; k < g.rev_off[v + 1]; k++) act[g.rev_src[k]] = 1;
+  for (uint32_t v0 = blockIdx.x * blockDim.x + threadIdx.x - lane; v0 < n; v0 += stride) {
+    const uint32_t v = v0 + lane;
+    bool set = false;
+    uint32_t pb = 0, pe = 0;
+    if (v < n && sb.oncyc[v] && sb.sum[lo[v]] < 0 && f[v] != top) {
+      f[v] = top;
+      mine++;
+      set = true;
+      pb = g.rev_off[v];
+      pe = g.rev_off[v + 1];
+      if (pe - pb <= SEED_SHORT)
+        for (uint32_t k = pb; k < pe; k++) act[g.rev_src[k]] = 1;
+    }
+    unsigned long long longs = __ballot(set && pe - pb > SEED_SHORT);
+    while (longs) {
+      const uint32_t src = (uint32_t)__ffsll((long long)longs) - 1;
+      longs &= longs - 1;
+      const uint32_t b = __shfl(pb, (int)src, WAVE), e = __shfl(pe, (int)src, WAVE);
+      for (uint32_t k = b + lane; k < e; k += WAVE) act[g.rev_src[k]] = 1;
+    }
   }
   if (mine) atomicAdd(sb.count, mine);
 }

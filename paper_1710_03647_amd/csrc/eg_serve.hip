@@ -13,7 +13,9 @@
 // predecessor lists on a side stream; init and publication of the slot on the
 // main stream, so a newcomer starts at the next epoch while the others keep
 // running), retires finished games (result conversion, copy to the ticket,
-// slot and arena freed), and drops cancelled ones.  The per-game arithmetic is
+// slot and arena freed), and drops cancelled ones.  With top_seeding a game
+// gets one seeding pass (negative cycles that player 1 can force set to TOP,
+// exact) between its init and its first epoch.  The per-game arithmetic is
 // the single-game kernel's tile code, so a game's credits do not depend on
 // what it shares the device with.
 #include <string.h>
@@ -305,6 +307,13 @@ int Server::admit_one(Ticket* t) {
   if (!e) e = hipStreamWaitEvent(main, ev_upload, 0);
   if (!e) e = hipMemsetAsync(dg.ctrl, 0, 4 * C_WORDS, main);
   if (!e) e = launch_init(dg, vbits, 0, (int)nblk, main);
+  if (!e && cfg.top_seeding) {
+    // one seeding pass before the first round; its scratch is the staging
+    // part of the range, free once the upload (side stream) has completed
+    SeedBuf sb{};
+    bind_seed(sb, staging, t->n);
+    e = launch_seed(dg, vbits, sb, 1, main);
+  }
   // publish: descriptor, zero counters, mode and first round, then the state
   h_games[slot] = dg;
   h_words[4 * slot] = SLOT_RUN;
@@ -550,8 +559,9 @@ int server_submit(Server* s, const eg_game_desc* desc, hipStream_t stream, eg_ti
   t->m = desc->m;
   t->W = desc->W;
   const size_t nblk = (size_t)std::max<int64_t>(1, std::min<int64_t>(64, ((int64_t)desc->n + TILE_VERTICES - 1) / TILE_VERTICES));
-  t->footprint = align_up(plan_layout(desc->n, desc->m, t->prep.info.value_bits, nblk).total) +
-                 staging_bytes(desc->n, desc->m, true);
+  size_t scratch = staging_bytes(desc->n, desc->m, true);
+  if (s->cfg.top_seeding) scratch = std::max(scratch, seed_bytes(desc->n));
+  t->footprint = align_up(plan_layout(desc->n, desc->m, t->prep.info.value_bits, nblk).total) + scratch;
   if (t->footprint > s->arena.capacity())
     return set_err(EG_ENOMEM, "the game needs " + std::to_string(t->footprint) + " bytes, the HBM budget is " +
                                   std::to_string(s->arena.capacity()));

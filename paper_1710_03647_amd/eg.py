@@ -28,7 +28,7 @@ ERROR_NAMES = {EG_EINVAL: "EG_EINVAL", EG_ENOMEM: "EG_ENOMEM", EG_EDEVICE: "EG_E
                EG_ECANCELED: "EG_ECANCELED", EG_PENDING: "EG_PENDING"}
 
 EXPORTS = ["eg_ctx_create", "eg_ctx_destroy", "eg_check", "eg_create", "eg_destroy", "eg_solve",
-           "eg_solve_ex", "eg_set_measure", "eg_strategy", "eg_submit", "eg_poll", "eg_cancel", "eg_wait", "eg_solve_batch",
+           "eg_solve_ex", "eg_solve_seeded_noalloc", "eg_set_measure", "eg_strategy", "eg_submit", "eg_poll", "eg_cancel", "eg_wait", "eg_solve_batch",
            "eg_last_error"]
 
 
@@ -110,6 +110,7 @@ def lib():
         L.eg_destroy.argtypes = [vp]
         L.eg_solve.argtypes = [vp, vp, P(eg_stats)]
         L.eg_solve_ex.argtypes = [vp, P(eg_solve_opts), vp, P(eg_stats)]
+        L.eg_solve_seeded_noalloc.argtypes = [vp, P(eg_solve_opts), vp, P(eg_stats)]
         L.eg_set_measure.argtypes = [vp, vp]
         L.eg_strategy.argtypes = [vp, vp, P(ctypes.c_double)]
         L.eg_submit.argtypes = [vp, P(eg_game_desc), P(ctypes.c_uint64)]
@@ -294,6 +295,19 @@ class Game:
         opts = eg_solve_opts(max_rounds, time_budget_s, 1 if resume else 0, 0)
         rc = lib().eg_solve_ex(self.handle, ctypes.byref(opts), _ptr(out), ctypes.byref(st))
         if rc != EG_OK and not (allow_timeout and rc == EG_ETIMEDOUT):
+            raise _err(rc, self.ctx.handle)
+        return out, st.to_dict(), rc
+
+    def solve_noalloc(self, out=None, max_rounds: int = 0, time_budget_s: float = 0.0, resume: bool = False):
+        """eg_solve_seeded_noalloc: a seeded solve that allocates nothing (its
+        seeding scratch is the library's static per-device array).  Returns
+        (credits int64[n], stats dict, status)."""
+        if out is None:
+            out = np.empty(self.n, dtype=np.int64)
+        st = eg_stats()
+        opts = eg_solve_opts(max_rounds, time_budget_s, 1 if resume else 0, 0)
+        rc = lib().eg_solve_seeded_noalloc(self.handle, ctypes.byref(opts), _ptr(out), ctypes.byref(st))
+        if rc != EG_OK:
             raise _err(rc, self.ctx.handle)
         return out, st.to_dict(), rc
 

@@ -208,3 +208,14 @@ def test_submit_device_pointers(oracle_mod):
         for game, t in zip(games, tickets):
             rc, f, st = ctx.wait(t, game.n)
             pins.expect_equal(f, oracle_mod.solve(game).f, f"{game.name}: device-pointer submit")
+
+
+def test_seeded_serving_matches_oracle(oracle_mod):
+    """Serving with top_seeding: each admitted game gets a seeding pass before
+    its first round; the credits stay the oracle's."""
+    games = mix_games()
+    with eg.Context(0, hbm_budget_bytes=2 * GiB, max_slots=6, top_seeding=1) as ctx:
+        tickets = [ctx.submit(g) for g in games]
+        for g, t in zip(games, tickets):
+            rc, f, st = ctx.wait(t, g.n)
+            pins.expect_equal(f, oracle_mod.solve(g).f, f"{g.name}: seeded serving")

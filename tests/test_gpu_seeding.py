@@ -78,3 +78,32 @@ def test_seeded_resume_and_repeat(sctx, oracle_mod):
         g.set_measure(np.minimum(want, noise))
         f, _, _ = g.solve(resume=True)
         pins.expect_equal(f, want, "resume")
+
+
+def test_negative_self_loop_of_player1_is_seeded(sctx, oracle_mod):
+    """A player-1 vertex with a negative self-loop loses whatever else it can
+    reach: the first seeding pass sets it to TOP even though another of its
+    edges has a larger term (plainly it would climb for about B / 2 rounds)."""
+    game = synth.make_game(3, [(0, 0, -1), (0, 1, -100), (1, 2, 0), (2, 2, 0)], [1, 1, 0], W=100)
+    f, st = seeded_solve(sctx, game)
+    pins.expect_equal(f, oracle_mod.solve(game).f, "player-1 negative self-loop")
+    assert f[0] == TOP and st["seeded"] >= 1 and st["rounds"] <= 4
+    with eg.Context(0) as plain:
+        f0, st0 = seeded_solve(plain, game)
+    pins.expect_equal(f0, f, "plain")
+    assert st0["rounds"] > 50
+
+
+def test_seeding_hub_rows(sctx, oracle_mod):
+    """Player-1 hubs whose rows are scanned by a whole wave: rows of 33 to
+    several thousand edges, chosen edge late in the row, ties on the term."""
+    rows = []
+    n = 64
+    for v in range(n):
+        deg = 1 + (v * 97) % 3000 if v % 3 == 0 else 1 + v % 5
+        rows.append([((v * 31 + 7 * k) % n, ((k * 13 + v) % 41) - 20) for k in range(deg)])
+    edges = [(v, t, w) for v, row in enumerate(rows) for t, w in row]
+    owner = [1 if v % 2 == 0 else 0 for v in range(n)]
+    game = synth.make_game(n, edges, owner, W=20, name="hub-rows")
+    f, st = seeded_solve(sctx, game)
+    pins.expect_equal(f, oracle_mod.solve(game).f, "hub rows")

@@ -1,0 +1,63 @@
+"""The seeded solve that allocates nothing (eg_solve_seeded_noalloc), called
+through the C-ABI, against eg_solve_ex with TOP seeding on the same games:
+identical credits on two calls in a row, the second on a smaller game, and
+the oracle's credits; device memory does not change across a call; games
+beyond the static scratch are refused."""
+import numpy as np
+import pytest
+
+import pins
+from paper_1710_03647_amd import eg, synth
+
+pytestmark = pytest.mark.gpu
+MAX_N = 1 << 22  # EG_NOALLOC_MAX_N
+
+
+def seeded_reference(game):
+    with eg.Context(0, top_seeding=1) as c:
+        with c.create(game) as g:
+            f, st, rc = g.solve()
+    return f
+
+
+def test_noalloc_equals_seeded_solve_twice(oracle_mod):
+    games = [synth.gen_rmat(16, 16, seed=3), synth.gen_uniform(3000, 4, 30, 9)]  # the second is smaller
+    with eg.Context(0) as ctx:
+        for game in games:
+            want = seeded_reference(game)
+            with ctx.create(game) as g:
+                f, st, rc = g.solve_noalloc()
+                assert rc == eg.EG_OK and st["seed_passes"] >= 1
+                pins.expect_equal(f, want, f"{game.name}: no-alloc vs seeded eg_solve_ex")
+                pins.expect_equal(f, oracle_mod.solve(game).f, f"{game.name}: no-alloc vs oracle")
+                # the game's ordinary solve afterwards uses its own scratch again
+                f2, _, _ = g.solve()
+                pins.expect_equal(f2, want, f"{game.name}: plain solve after the no-alloc one")
+
+
+def test_noalloc_leaves_device_memory_alone():
+    import torch
+
+    game = synth.gen_rmat(14, 16, seed=3)
+    with eg.Context(0) as ctx:
+        with ctx.create(game) as warm:
+            warm.solve_noalloc()  # the device's scratch array is in place from here on
+        with ctx.create(game) as g:
+            torch.cuda.synchronize()
+            free0 = torch.cuda.mem_get_info()[0]
+            f, st, rc = g.solve_noalloc()
+            torch.cuda.synchronize()
+            free1 = torch.cuda.mem_get_info()[0]
+    assert free1 == free0, f"device memory changed by {free0 - free1} bytes across the call"
+
+
+def test_noalloc_refuses_games_beyond_the_scratch():
+    n = MAX_N + 1
+    game = synth.Game(n=n, off=np.arange(n + 1, dtype=np.int64), tgt=np.arange(n, dtype=np.int32),
+                      w=np.zeros(n, dtype=np.int32), owner=np.zeros(n, dtype=np.uint8), W=0, name="too-large")
+    with eg.Context(0) as ctx:
+        with ctx.create(game) as g:
+            with pytest.raises(eg.EgError) as ei:
+                g.solve_noalloc()
+            assert ei.value.code == eg.EG_EINVAL
+            assert "EG_NOALLOC_MAX_N" in str(ei.value)
