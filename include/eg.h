@@ -93,6 +93,13 @@ typedef struct {
                                 in-degree is >= 64x the average (n >= 4096) and dense rounds are
                                 unsliced with tiles cut, 1 = never, 2 = always; credits are always
                                 returned in the caller's numbering */
+  int p1_filter;             /* 1 = the player-1 frontier filter (Alg. 1's predecessor test, Sec. 3.1):
+                                when v's value rises, a player-1 predecessor p joins the next active set
+                                only if f(p) < f(v) (-) w(p, v) (every player-0 predecessor still joins,
+                                as in Alg. 3).  Exact under the in-place parallel updates (values only
+                                rise, so a satisfied test stays satisfied until f(v) rises again, which
+                                tests again); the credits do not change, only the work.  Costs 4 bytes
+                                per edge of device memory (the weights of the predecessor lists) */
 } eg_config;
 
 /* A game in CSR form.  Out-edges of v are e in [offsets[v], offsets[v+1]),
@@ -135,6 +142,7 @@ typedef struct {
   uint64_t seed_passes;   /* seeding passes run */
   uint64_t all_rounds;    /* dense rounds that lifted every vertex without activating (frontier ~ V) */
   double t_seed;          /* eg_solve: device time of the seeding passes (top_seeding), seconds */
+  uint64_t filtered_preds; /* predecessor entries the player-1 frontier filter kept out (p1_filter) */
 } eg_stats;
 
 /* What eg_check derives from a valid game. */

@@ -208,6 +208,7 @@ int eg_ctx_create(const eg_config* cfg, eg_ctx** out) {
   }
   if (c.blocks_per_cu < 0 || c.blocks_per_cu > 32 || c.dense_div < 0 || c.small_limit < 0 || c.small_limit > 65536 ||
       c.partition < 0 || c.partition > 2 || c.top_seeding < 0 || c.top_seeding > 1 || c.seg_edges < -1 ||
+      c.p1_filter < 0 || c.p1_filter > 1 ||
       c.relabel < 0 || c.relabel > 2 ||
       (c.seg_edges > 0 && c.seg_edges < 256)) {
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
@@ -301,13 +302,13 @@ uint32_t choose_parts(int32_t n, int64_t, int, int mode) {
   return 1;
 }
 
-GameLayout plan_layout(int32_t n, int64_t m, int vbits, size_t nblk, uint32_t nparts) {
+GameLayout plan_layout(int32_t n, int64_t m, int vbits, size_t nblk, uint32_t nparts, bool filter) {
   const size_t nn = (size_t)n, mm = (size_t)m, vb = (size_t)vbits / 8;
   const bool pe = nparts > 1;
   const size_t sizes[L_N] = {4 * (nn + 1), 8 * mm, 4 * (nn + 1), 4 * mm, vb * nn, 2 * align_up(nn + 4), 4 * nn,
                              4 * nn, 8 * nn, 4 * C_WORDS, 8 * S_WORDS, 4 * ((nn + 31) / 32), 4 * nblk,
                              8 * S_WORDS * nblk, pe ? 8 * mm : 0, pe ? 4 * partition_scratch_words(n, nparts) : 0,
-                             pe ? 4 * ((nn + 31) / 32) : 0, pe ? vb * nn * nparts : 0};
+                             pe ? 4 * ((nn + 31) / 32) : 0, pe ? vb * nn * nparts : 0, filter ? 4 * mm : 0};
   GameLayout L{};
   for (int i = 0; i < L_N; i++) {
     L.off[i] = L.total;
@@ -316,7 +317,8 @@ GameLayout plan_layout(int32_t n, int64_t m, int vbits, size_t nblk, uint32_t np
   return L;
 }
 
-void bind_layout(DevGame& dg, char* base, const GameLayout& L, int32_t n, int64_t m, int vbits, uint32_t nparts) {
+void bind_layout(DevGame& dg, char* base, const GameLayout& L, int32_t n, int64_t m, int vbits, uint32_t nparts,
+                 bool filter) {
   dg.n = n;
   dg.m = (uint32_t)m;
   dg.rs = (uint32_t*)(base + L.off[L_RS]);
@@ -340,6 +342,7 @@ void bind_layout(DevGame& dg, char* base, const GameLayout& L, int32_t n, int64_
   dg.poff = (const uint32_t*)(base + L.off[L_POFF]);
   dg.own_bits = (const uint32_t*)(base + L.off[L_OWNB]);
   dg.part = base + L.off[L_PART];
+  dg.rev_w = filter ? (const int32_t*)(base + L.off[L_RW]) : nullptr;
 }
 
 size_t staging_bytes(int32_t n, int64_t m, bool host_inputs) {
@@ -389,7 +392,7 @@ hipError_t upload_game(const eg_game_desc* d, const HostPrep& prep, DevGame& dg,
     return r;
   if (after_layout && (r = hipEventRecord(after_layout, s))) return r;
   if ((r = launch_reverse_csr(dg.rs, dg.edges, d->n, (uint32_t)mm, (uint32_t*)dg.rev_off, (int32_t*)dg.rev_src,
-                              cursor, scan_tmp, scan_words, s)) != hipSuccess)
+                              (int32_t*)dg.rev_w, cursor, scan_tmp, scan_words, s)) != hipSuccess)
     return r;
   if (dg.nparts > 1) return launch_partition(dg, d_own, cursor, scan_tmp, scan_words, s);
   return hipSuccess;
@@ -493,7 +496,8 @@ int eg_create(eg_ctx* ctx, const eg_game_desc* desc, eg_game** out, eg_stats* st
   g->grid = (int)nblk;
   g->part_grid = std::max(8, ctx->grid / 8 * 8);
   const uint32_t nparts = eg::choose_parts(g->n, g->m, g->vbits, ctx->cfg.partition);
-  const eg::GameLayout L = eg::plan_layout(g->n, g->m, g->vbits, nblk, nparts);
+  const bool filter = ctx->cfg.p1_filter != 0;
+  const eg::GameLayout L = eg::plan_layout(g->n, g->m, g->vbits, nblk, nparts, filter);
   hipError_t e = hipMalloc(&g->arena, L.total);
   if (e != hipSuccess) {
     game_free(g);
@@ -501,7 +505,7 @@ int eg_create(eg_ctx* ctx, const eg_game_desc* desc, eg_game** out, eg_stats* st
   }
   g->arena_bytes = L.total;
   eg::DevGame& dg = g->dg;
-  eg::bind_layout(dg, (char*)g->arena, L, g->n, g->m, g->vbits, nparts);
+  eg::bind_layout(dg, (char*)g->arena, L, g->n, g->m, g->vbits, nparts, filter);
   g->out64 = (int64_t*)((char*)g->arena + L.off[eg::L_OUT]);
   dg.bound = g->bound;
   dg.top = g->bound + prep.clamp + 1;
@@ -802,6 +806,7 @@ static int solve_impl(eg_game* g, const eg_solve_opts* opts, int64_t* credits, e
     st->pushes = g->h_stats[eg::S_PUSHES];
     st->changes = g->h_stats[eg::S_CHANGES];
     st->scanned_preds = g->h_stats[eg::S_SCANNED];
+    st->filtered_preds = g->h_stats[eg::S_FILTERED];
     float ms = 0;
     (void)hipEventElapsedTime(&ms, g->ev[0], g->ev[1]);
     st->t_solve = ms * 1e-3;

@@ -25,7 +25,8 @@ enum Ctrl : int {
   C_WORDS = 8
 };
 // counters per block (slots) and totals (stats), uint64
-enum Stat : int { S_LIFTS = 0, S_EDGES = 1, S_PUSHES = 2, S_CHANGES = 3, S_SCANNED = 4, S_WORDS = 5 };
+// S_FILTERED: predecessor entries the player-1 frontier filter left out
+enum Stat : int { S_LIFTS = 0, S_EDGES = 1, S_PUSHES = 2, S_CHANGES = 3, S_SCANNED = 4, S_FILTERED = 5, S_WORDS = 6 };
 
 // Everything a kernel needs to see of one game (passed by value).
 struct DevGame {
@@ -65,6 +66,10 @@ struct DevGame {
   void* gkey;               // n keys (width vbits) combined over the segments of cut tiles
   const int32_t* perm;      // n: internal id of each caller vertex (nullptr: ids are the caller's)
   uint32_t lanes_ok;        // small-degree tiles may use one lane per vertex (game fits the caches)
+  // player-1 frontier filter (Alg. 1's predecessor test, player-1 predecessors):
+  // a player-1 predecessor p of a changed v joins the next active set only if
+  // f(p) < f(v) (-) w(p, v); nullptr: every predecessor joins (Alg. 3)
+  const int32_t* rev_w;     // m: weight of the edge of each predecessor entry (stored, clamped)
 };
 
 // A game whose edges and values fit in this many bytes may lift small-degree
@@ -119,15 +124,16 @@ struct BatchTable {
 // Device layout of one game: every array in one allocation.
 enum LayoutPart : int {
   L_RS, L_EDGES, L_ROFF, L_RSRC, L_F, L_ACT, L_WL0, L_WL1, L_OUT, L_CTRL, L_STATS, L_ACTBITS, L_BLK, L_SLOTS,
-  L_PEDGES, L_POFF, L_OWNB, L_PART, L_N
+  L_PEDGES, L_POFF, L_OWNB, L_PART, L_RW, L_N
 };
 struct GameLayout {
   size_t off[L_N];
   size_t total;
 };
-GameLayout plan_layout(int32_t n, int64_t m, int vbits, size_t nblocks, uint32_t nparts = 1);
+// filter: room for the reverse weights of the player-1 frontier filter
+GameLayout plan_layout(int32_t n, int64_t m, int vbits, size_t nblocks, uint32_t nparts = 1, bool filter = false);
 void bind_layout(DevGame& dg, char* base, const GameLayout& L, int32_t n, int64_t m, int vbits,
-                 uint32_t nparts = 1);
+                 uint32_t nparts = 1, bool filter = false);
 uint32_t choose_parts(int32_t n, int64_t m, int vbits, int mode);
 hipError_t launch_partition(const DevGame& dg, const uint8_t* owner_bits, uint32_t* cursor, uint32_t* scan_tmp,
                             size_t scan_words, hipStream_t s);
@@ -175,8 +181,9 @@ hipError_t launch_gkey_init(const DevGame& g, int vbits, hipStream_t s);
 hipError_t launch_layout(const int64_t* off, const uint8_t* owner_bits, const int32_t* tgt,
                          const int32_t* w, int32_t n, uint32_t m, int32_t wclamp, uint32_t* rs,
                          int2* edges, hipStream_t s);
+// rev_w (nullable): also the weight of each predecessor entry's edge
 hipError_t launch_reverse_csr(const uint32_t* rs, const int2* edges, int32_t n, uint32_t m,
-                              uint32_t* rev_off, int32_t* rev_src, uint32_t* cursor,
+                              uint32_t* rev_off, int32_t* rev_src, int32_t* rev_w, uint32_t* cursor,
                               uint32_t* scan_tmp, size_t scan_tmp_words, hipStream_t s);
 size_t scan_tmp_words(size_t count);
 

@@ -162,15 +162,17 @@ __device__ __forceinline__ int32_t source_of(const uint32_t* rs, int32_t n, uint
 // Each thread takes a contiguous run of edges: one binary search finds the
 // source of its first edge, after which the source only moves forward.
 __global__ void k_scatter_preds(const uint32_t* rs, const int2* edges, int32_t n, uint32_t m,
-                                uint32_t chunk, uint32_t* cursor, int32_t* rev_src) {
+                                uint32_t chunk, uint32_t* cursor, int32_t* rev_src, int32_t* rev_w) {
   const uint64_t first = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * chunk;
   if (first >= m) return;
   const uint32_t last = (uint32_t)std::min<uint64_t>(m, first + chunk);
   int32_t v = source_of(rs, n, (uint32_t)first);
   for (uint32_t e = (uint32_t)first; e < last; e++) {
     while ((rs[v + 1] & ROW_MASK) <= e) v++;
-    const uint32_t slot = atomicAdd(&cursor[edges[e].x], 1u);
+    const int2 ed = edges[e];
+    const uint32_t slot = atomicAdd(&cursor[ed.x], 1u);
     rev_src[slot] = v;
+    if (rev_w) rev_w[slot] = ed.y;
   }
 }
 
@@ -241,7 +243,7 @@ hipError_t launch_partition(const DevGame& dg, const uint8_t*, uint32_t* cursor,
 }
 
 hipError_t launch_reverse_csr(const uint32_t* rs, const int2* edges, int32_t n, uint32_t m,
-                              uint32_t* rev_off, int32_t* rev_src, uint32_t* cursor,
+                              uint32_t* rev_off, int32_t* rev_src, int32_t* rev_w, uint32_t* cursor,
                               uint32_t* scan_tmp, size_t scan_tmp_words_avail, hipStream_t s) {
   if (scan_tmp_words_avail < scan_tmp_words((size_t)n + 1)) return hipErrorInvalidValue;
   hipError_t e = hipMemsetAsync(cursor, 0, sizeof(uint32_t) * ((size_t)n + 1), s);
@@ -256,7 +258,7 @@ hipError_t launch_reverse_csr(const uint32_t* rs, const int2* edges, int32_t n, 
     const uint32_t chunk = 16;
     const int grid_s = (int)(((uint64_t)m + (uint64_t)chunk * BLOCK - 1) / ((uint64_t)chunk * BLOCK));
     hipLaunchKernelGGL(k_scatter_preds, dim3(grid_s), dim3(BLOCK), 0, s, rs, edges, n, m, chunk, cursor,
-                       rev_src);
+                       rev_src, rev_w);
   }
   return hipGetLastError();
 }
@@ -349,6 +351,7 @@ struct RoundShared {
   V key[BLOCK];              // running min of the per-edge keys (negated terms for player 1)
   uint32_t ppre[BLOCK + 1];  // exclusive prefix of in-degrees of the tile's changed vertices
   uint32_t pbeg[BLOCK];      // their predecessor-list starts
+  V pval[BLOCK];             // their new values (player-1 frontier filter)
   uint32_t wsum[BLOCK / WAVE];
   uint32_t wbig[BLOCK / WAVE];  // per wave: some active vertex has more than LANE_DEG out-edges
   // push stages list entries across the tiles of a sparse round; term is used
@@ -536,19 +539,52 @@ __device__ __forceinline__ uint32_t contig_base(const DevGame& g, uint32_t t, ui
 
 // Predecessor entries [x0, x0 + J * BLOCK) of the tile's changed vertices,
 // loaded the same way, then activated for the next round.
+// With the player-1 frontier filter (g.rev_w set), a player-1 predecessor p of
+// a changed v is left out when f(p) >= f(v) (-) w(p, v) already holds (Alg. 1's
+// test, Sec. 3.1): lifting p cannot raise it through this edge.  In the device
+// encoding the term is TOP (> B) when f(v) - w > B, else max(0, f(v) - w); a
+// TOP f(p) satisfies every test.  Exact under in-place updates: f(p) only
+// rises, so a test that holds now holds until f(v) rises again, and that rise
+// tests again; a stale, lower f(p) only lets more in.
 template <bool DENSE, typename V, int J>
 __device__ __forceinline__ void scan_preds(const DevGame& g, RoundShared<V>& sh, uint32_t x0, uint32_t P,
                                            uint8_t* act_next, int32_t* wl_out, uint32_t* cnt_out,
-                                           unsigned long long& pushes) {
+                                           unsigned long long& pushes, unsigned long long& filtered) {
   const uint32_t tid = threadIdx.x;
   int32_t pr[J];
+  uint32_t k[J], slot[J];
 #pragma unroll
   for (int j = 0; j < J; j++) {
     const uint32_t x = x0 + j * BLOCK + tid;
     const uint32_t xc = x < P ? x : P - 1;
     const uint32_t s = find_range(sh.ppre, xc);
-    pr[j] = load_stream(g.rev_src + sh.pbeg[s] + (xc - sh.ppre[s]));
+    slot[j] = s;
+    k[j] = sh.pbeg[s] + (xc - sh.ppre[s]);
+    pr[j] = load_stream(g.rev_src + k[j]);
     if (x >= P) pr[j] = -1;
+  }
+  if (g.rev_w) {
+    const V* f = (const V*)g.f;
+    const V bound = (V)g.bound, top = (V)g.top;
+    int32_t w[J];
+    uint32_t raw[J];
+#pragma unroll
+    for (int j = 0; j < J; j++) {
+      w[j] = load_stream(g.rev_w + k[j]);
+      raw[j] = g.rs[pr[j] >= 0 ? pr[j] : 0];
+    }
+#pragma unroll
+    for (int j = 0; j < J; j++) {
+      if (pr[j] >= 0 && (raw[j] & OWNER_BIT)) {
+        const V fp = f[pr[j]];
+        const V t = sh.pval[slot[j]] - (V)w[j];
+        const bool holds = fp == top || (t <= bound && fp >= (t > V(0) ? t : V(0)));
+        if (holds) {
+          pr[j] = -1;
+          filtered++;
+        }
+      }
+    }
   }
 #pragma unroll
   for (int j = 0; j < J; j++) activate<DENSE>(g, sh, pr[j] >= 0, pr[j], act_next, wl_out, cnt_out, pushes);
@@ -608,7 +644,7 @@ __global__ __launch_bounds__(BLOCK) void k_compact(DevGame g, uint32_t r) {
 
 // Per-thread counters of a round (summed per block at the end).
 struct Counters {
-  unsigned long long lifts = 0, edges = 0, changes = 0, pushes = 0, scanned = 0;
+  unsigned long long lifts = 0, edges = 0, changes = 0, pushes = 0, scanned = 0, filtered = 0;
 };
 
 // One tile of a round of Alg. 3 (block-uniform call).  The tile holds TILE
@@ -746,6 +782,7 @@ __device__ __forceinline__ void round_tile(const DevGame& g, RoundShared<V>& sh,
   block_sync();
 
   uint32_t ideg = 0;
+  V nval = 0;
   if (v >= 0) {
     const V k = sh.key[tid];
     V nv = (raw & OWNER_BIT) ? -k : k;
@@ -759,6 +796,7 @@ __device__ __forceinline__ void round_tile(const DevGame& g, RoundShared<V>& sh,
     c.edges += deg;
     if (nv != old) {
       f[v] = nv;
+      nval = nv;
       c.changes++;
       ideg = pe - pb;
     }
@@ -769,18 +807,19 @@ __device__ __forceinline__ void round_tile(const DevGame& g, RoundShared<V>& sh,
   sh.ppre[tid] = pex;
   if (tid == BLOCK - 1) sh.ppre[BLOCK] = P;
   sh.pbeg[tid] = pb;
+  sh.pval[tid] = nval;
   c.scanned += ideg;
   block_sync();
   for (uint32_t x0 = 0; x0 < P; x0 += BLOCK * UNROLL) {
     switch (std::min<uint32_t>((P - x0 + BLOCK - 1) / BLOCK, UNROLL)) {
-      case 1: scan_preds<DENSE, V, 1>(g, sh, x0, P, act_next, wl_out, cnt_out, c.pushes); break;
-      case 2: scan_preds<DENSE, V, 2>(g, sh, x0, P, act_next, wl_out, cnt_out, c.pushes); break;
-      case 3: scan_preds<DENSE, V, 3>(g, sh, x0, P, act_next, wl_out, cnt_out, c.pushes); break;
-      case 4: scan_preds<DENSE, V, 4>(g, sh, x0, P, act_next, wl_out, cnt_out, c.pushes); break;
-      case 5: scan_preds<DENSE, V, 5>(g, sh, x0, P, act_next, wl_out, cnt_out, c.pushes); break;
-      case 6: scan_preds<DENSE, V, 6>(g, sh, x0, P, act_next, wl_out, cnt_out, c.pushes); break;
-      case 7: scan_preds<DENSE, V, 7>(g, sh, x0, P, act_next, wl_out, cnt_out, c.pushes); break;
-      default: scan_preds<DENSE, V, UNROLL>(g, sh, x0, P, act_next, wl_out, cnt_out, c.pushes); break;
+      case 1: scan_preds<DENSE, V, 1>(g, sh, x0, P, act_next, wl_out, cnt_out, c.pushes, c.filtered); break;
+      case 2: scan_preds<DENSE, V, 2>(g, sh, x0, P, act_next, wl_out, cnt_out, c.pushes, c.filtered); break;
+      case 3: scan_preds<DENSE, V, 3>(g, sh, x0, P, act_next, wl_out, cnt_out, c.pushes, c.filtered); break;
+      case 4: scan_preds<DENSE, V, 4>(g, sh, x0, P, act_next, wl_out, cnt_out, c.pushes, c.filtered); break;
+      case 5: scan_preds<DENSE, V, 5>(g, sh, x0, P, act_next, wl_out, cnt_out, c.pushes, c.filtered); break;
+      case 6: scan_preds<DENSE, V, 6>(g, sh, x0, P, act_next, wl_out, cnt_out, c.pushes, c.filtered); break;
+      case 7: scan_preds<DENSE, V, 7>(g, sh, x0, P, act_next, wl_out, cnt_out, c.pushes, c.filtered); break;
+      default: scan_preds<DENSE, V, UNROLL>(g, sh, x0, P, act_next, wl_out, cnt_out, c.pushes, c.filtered); break;
     }
   }
 }
@@ -897,6 +936,7 @@ __device__ __forceinline__ void round_seg(const DevGame& g, RoundShared<V>& sh, 
     if (tid == 0) g.tile_done[t] = 0;
   }
   uint32_t ideg = 0;
+  V nval = 0;
   if (v >= 0) {
     if (!ALL) act_cur[v] = 0;  // consumed
     V nv = (raw & OWNER_BIT) ? -k : k;
@@ -906,6 +946,7 @@ __device__ __forceinline__ void round_seg(const DevGame& g, RoundShared<V>& sh, 
     c.edges += deg;
     if (nv != old) {
       f[v] = nv;
+      nval = nv;
       c.changes++;
       ideg = pe - pb;
     }
@@ -916,18 +957,19 @@ __device__ __forceinline__ void round_seg(const DevGame& g, RoundShared<V>& sh, 
   sh.ppre[tid] = pex;
   if (tid == BLOCK - 1) sh.ppre[BLOCK] = P;
   sh.pbeg[tid] = pb;
+  sh.pval[tid] = nval;
   c.scanned += ideg;
   block_sync();
   for (uint32_t x0 = 0; x0 < P; x0 += BLOCK * UNROLL) {
     switch (std::min<uint32_t>((P - x0 + BLOCK - 1) / BLOCK, UNROLL)) {
-      case 1: scan_preds<true, V, 1>(g, sh, x0, P, act_next, nullptr, nullptr, c.pushes); break;
-      case 2: scan_preds<true, V, 2>(g, sh, x0, P, act_next, nullptr, nullptr, c.pushes); break;
-      case 3: scan_preds<true, V, 3>(g, sh, x0, P, act_next, nullptr, nullptr, c.pushes); break;
-      case 4: scan_preds<true, V, 4>(g, sh, x0, P, act_next, nullptr, nullptr, c.pushes); break;
-      case 5: scan_preds<true, V, 5>(g, sh, x0, P, act_next, nullptr, nullptr, c.pushes); break;
-      case 6: scan_preds<true, V, 6>(g, sh, x0, P, act_next, nullptr, nullptr, c.pushes); break;
-      case 7: scan_preds<true, V, 7>(g, sh, x0, P, act_next, nullptr, nullptr, c.pushes); break;
-      default: scan_preds<true, V, UNROLL>(g, sh, x0, P, act_next, nullptr, nullptr, c.pushes); break;
+      case 1: scan_preds<true, V, 1>(g, sh, x0, P, act_next, nullptr, nullptr, c.pushes, c.filtered); break;
+      case 2: scan_preds<true, V, 2>(g, sh, x0, P, act_next, nullptr, nullptr, c.pushes, c.filtered); break;
+      case 3: scan_preds<true, V, 3>(g, sh, x0, P, act_next, nullptr, nullptr, c.pushes, c.filtered); break;
+      case 4: scan_preds<true, V, 4>(g, sh, x0, P, act_next, nullptr, nullptr, c.pushes, c.filtered); break;
+      case 5: scan_preds<true, V, 5>(g, sh, x0, P, act_next, nullptr, nullptr, c.pushes, c.filtered); break;
+      case 6: scan_preds<true, V, 6>(g, sh, x0, P, act_next, nullptr, nullptr, c.pushes, c.filtered); break;
+      case 7: scan_preds<true, V, 7>(g, sh, x0, P, act_next, nullptr, nullptr, c.pushes, c.filtered); break;
+      default: scan_preds<true, V, UNROLL>(g, sh, x0, P, act_next, nullptr, nullptr, c.pushes, c.filtered); break;
     }
   }
 }
@@ -1026,6 +1068,7 @@ __device__ __forceinline__ void block_counters(RoundShared<V>& sh, const Counter
   atomicAdd(&sh.st[S_CHANGES], c.changes);
   atomicAdd(&sh.st[S_PUSHES], c.pushes);
   atomicAdd(&sh.st[S_SCANNED], c.scanned);
+  atomicAdd(&sh.st[S_FILTERED], c.filtered);
   block_sync();
 }
 

@@ -293,9 +293,10 @@ int Server::admit_one(Ticket* t) {
   char* base = arena.base() + off;
   const int vbits = t->prep.info.value_bits;
   const size_t nblk = (size_t)std::max<int64_t>(1, std::min<int64_t>(64, ((int64_t)t->n + TILE_VERTICES - 1) / TILE_VERTICES));
-  const GameLayout L = plan_layout(t->n, t->m, vbits, nblk);
+  const bool filter = cfg.p1_filter != 0;
+  const GameLayout L = plan_layout(t->n, t->m, vbits, nblk, 1, filter);
   DevGame& dg = t->dg;
-  bind_layout(dg, base, L, t->n, t->m, vbits);
+  bind_layout(dg, base, L, t->n, t->m, vbits, 1, filter);
   dg.bound = t->prep.info.bound;
   dg.top = dg.bound + t->prep.clamp + 1;
   dg.lanes_ok = lanes_ok_for(t->n, t->m, vbits);
@@ -375,6 +376,7 @@ void Server::retire(int slot, bool finished) {
     s.pushes = h_st[slot * S_WORDS + S_PUSHES];
     s.changes = h_st[slot * S_WORDS + S_CHANGES];
     s.scanned_preds = h_st[slot * S_WORDS + S_SCANNED];
+    s.filtered_preds = h_st[slot * S_WORDS + S_FILTERED];
     s.t_solve = t->t_done - t->t_admit;
     s.t_queue = t->t_admit - t->t_arrive;
     s.t_latency = t->t_done - t->t_arrive;
@@ -561,7 +563,8 @@ int server_submit(Server* s, const eg_game_desc* desc, hipStream_t stream, eg_ti
   const size_t nblk = (size_t)std::max<int64_t>(1, std::min<int64_t>(64, ((int64_t)desc->n + TILE_VERTICES - 1) / TILE_VERTICES));
   size_t scratch = staging_bytes(desc->n, desc->m, true);
   if (s->cfg.top_seeding) scratch = std::max(scratch, seed_bytes(desc->n));
-  t->footprint = align_up(plan_layout(desc->n, desc->m, t->prep.info.value_bits, nblk).total) + scratch;
+  t->footprint = align_up(plan_layout(desc->n, desc->m, t->prep.info.value_bits, nblk, 1, s->cfg.p1_filter != 0).total) +
+                 scratch;
   if (t->footprint > s->arena.capacity())
     return set_err(EG_ENOMEM, "the game needs " + std::to_string(t->footprint) + " bytes, the HBM budget is " +
                                   std::to_string(s->arena.capacity()));

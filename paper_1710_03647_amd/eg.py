@@ -45,7 +45,7 @@ class eg_config(ctypes.Structure):
                 ("time_budget_s", ctypes.c_double), ("max_pending", ctypes.c_int),
                 ("partition", ctypes.c_int), ("blocks_per_cu", ctypes.c_int), ("dense_div", ctypes.c_int),
                 ("small_limit", ctypes.c_int), ("top_seeding", ctypes.c_int), ("seg_edges", ctypes.c_int),
-                ("relabel", ctypes.c_int)]
+                ("relabel", ctypes.c_int), ("p1_filter", ctypes.c_int)]
 
 
 class eg_game_desc(ctypes.Structure):
@@ -64,7 +64,8 @@ class eg_stats(ctypes.Structure):
                 ("t_round_kernels", ctypes.c_double), ("t_queue", ctypes.c_double),
                 ("t_latency", ctypes.c_double), ("launched_rounds", ctypes.c_uint64),
                 ("dense_rounds", ctypes.c_uint64), ("seeded", ctypes.c_uint64), ("seed_passes", ctypes.c_uint64),
-                ("all_rounds", ctypes.c_uint64), ("t_seed", ctypes.c_double)]
+                ("all_rounds", ctypes.c_uint64), ("t_seed", ctypes.c_double),
+                ("filtered_preds", ctypes.c_uint64)]
 
     def to_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -191,11 +192,12 @@ class Context:
     def __init__(self, device: int = 0, stream=None, hbm_budget_bytes: int = 0, max_slots: int = 0,
                  bound_mode: int = EG_BOUND_NW, max_rounds: int = 0, time_budget_s: float = 0.0,
                  max_pending: int = 0, partition: int = 0, blocks_per_cu: int = 0, dense_div: int = 0,
-                 small_limit: int = 0, top_seeding: int = 0, seg_edges: int = 0, relabel: int = 0):
+                 small_limit: int = 0, top_seeding: int = 0, seg_edges: int = 0, relabel: int = 0,
+                 p1_filter: int = 0):
         handle = getattr(stream, "cuda_stream", stream) or 0
         cfg = eg_config(device, handle, hbm_budget_bytes, max_slots, bound_mode, max_rounds, time_budget_s,
                         max_pending, partition, blocks_per_cu, dense_div, small_limit, int(top_seeding),
-                        seg_edges, relabel)
+                        seg_edges, relabel, int(p1_filter))
         p = ctypes.c_void_p()
         rc = lib().eg_ctx_create(ctypes.byref(cfg), ctypes.byref(p))
         if rc != EG_OK:
