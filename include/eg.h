@@ -100,6 +100,14 @@ typedef struct {
                                 rise, so a satisfied test stays satisfied until f(v) rises again, which
                                 tests again); the credits do not change, only the work.  Costs 4 bytes
                                 per edge of device memory (the weights of the predecessor lists) */
+  int scc_schedule;          /* 1 = the component schedule (the refinement proposed in Sec. 6): eg_solve
+                                first finds the strongly connected components of the game graph and the
+                                levels of their condensation (once per game, 13 bytes per vertex of device
+                                memory), then solves level by level from the sink components up, each
+                                level from all of its vertices, with predecessors on higher levels kept
+                                out of the active set until their level starts.  Exact (a level's
+                                successors outside it are already at their least-fixpoint values); the
+                                credits do not change, only the work.  eg_solve only (not serving) */
 } eg_config;
 
 /* A game in CSR form.  Out-edges of v are e in [offsets[v], offsets[v+1]),
@@ -143,6 +151,9 @@ typedef struct {
   uint64_t all_rounds;    /* dense rounds that lifted every vertex without activating (frontier ~ V) */
   double t_seed;          /* eg_solve: device time of the seeding passes (top_seeding), seconds */
   uint64_t filtered_preds; /* predecessor entries the player-1 frontier filter kept out (p1_filter) */
+  uint64_t scc_components; /* scc_schedule: strongly connected components of the game graph */
+  uint64_t scc_levels;     /* scc_schedule: levels of the condensation (sink components are level 0) */
+  double t_scc;            /* scc_schedule: wall time of finding them (first solve of the game only), seconds */
 } eg_stats;
 
 /* What eg_check derives from a valid game. */
@@ -242,6 +253,20 @@ int eg_set_measure(eg_game* g, const int64_t* f);
  * finite credit has no such edge (the measure is not a fixpoint).  Serialised
  * with the solves of the context. */
 int eg_strategy(eg_game* g, int32_t* choice, double* t_kernel);
+
+/* The strongly connected components of the game graph and the levels of their
+ * condensation, the order of the component schedule (the refinement proposed
+ * in Sec. 6; see eg_config.scc_schedule), computed on the device at the first
+ * call or schedule solve of g and kept with the game (13 bytes per vertex).
+ * comp, level (n entries each, caller-owned host memory, caller's numbering):
+ * comp[v] labels v's component (two vertices share a label exactly when each
+ * reaches the other; labels are vertex ids of the device numbering, so they
+ * equal the caller's ids only for games that are not renumbered); level[v] is
+ * 0 for components with no edge leaving them, else one more than the largest
+ * level among the components that v's component has edges into.  components,
+ * levels (nullable): their counts.  EG_EINVAL on a null game or array.
+ * Serialised with the solves of the context. */
+int eg_components(eg_game* g, int32_t* comp, int32_t* level, uint32_t* components, uint32_t* levels);
 
 /* Serving.  eg_submit copies the game into the context's pending queue and
  * returns at once with a ticket (EG_EBUSY if the queue is full, EG_EINVAL for

@@ -16,7 +16,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libeg.so")
 OBJDIR = os.path.join(PKG, "_build")
-SOURCES = ["eg_kernels.hip", "eg_api.hip", "eg_serve.hip", "eg_strategy.hip"]
+SOURCES = ["eg_kernels.hip", "eg_api.hip", "eg_serve.hip", "eg_strategy.hip", "eg_scc.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

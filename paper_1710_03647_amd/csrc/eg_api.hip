@@ -163,6 +163,10 @@ struct eg_game {
   void* perm_mem = nullptr;  // internal id of each caller vertex (renumbered games)
   eg::SeedBuf sb{};
   uint32_t* h_seed = nullptr;
+  void* scc_mem = nullptr;   // components and levels (component schedule), computed by the first such solve
+  uint32_t* h_scc = nullptr;
+  eg::SccBuf scc{};
+  eg::SccInfo scc_info{};
   bool at_fixpoint = false;  // the device measure is the least fixpoint (last solve returned EG_OK)
 };
 
@@ -208,7 +212,7 @@ int eg_ctx_create(const eg_config* cfg, eg_ctx** out) {
   }
   if (c.blocks_per_cu < 0 || c.blocks_per_cu > 32 || c.dense_div < 0 || c.small_limit < 0 || c.small_limit > 65536 ||
       c.partition < 0 || c.partition > 2 || c.top_seeding < 0 || c.top_seeding > 1 || c.seg_edges < -1 ||
-      c.p1_filter < 0 || c.p1_filter > 1 ||
+      c.p1_filter < 0 || c.p1_filter > 1 || c.scc_schedule < 0 || c.scc_schedule > 1 ||
       c.relabel < 0 || c.relabel > 2 ||
       (c.seg_edges > 0 && c.seg_edges < 256)) {
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
@@ -256,6 +260,8 @@ static void game_free(eg_game* g) {
   if (g->seg_mem) (void)hipFree(g->seg_mem);
   if (g->perm_mem) (void)hipFree(g->perm_mem);
   if (g->h_seed) (void)hipHostFree(g->h_seed);
+  if (g->scc_mem) (void)hipFree(g->scc_mem);
+  if (g->h_scc) (void)hipHostFree(g->h_scc);
   for (auto& e : g->ev)
     if (e) (void)hipEventDestroy(e);
   delete g;
@@ -345,10 +351,15 @@ void bind_layout(DevGame& dg, char* base, const GameLayout& L, int32_t n, int64_
   dg.rev_w = filter ? (const int32_t*)(base + L.off[L_RW]) : nullptr;
 }
 
-size_t staging_bytes(int32_t n, int64_t m, bool host_inputs) {
+size_t staging_bytes(int32_t n, int64_t m, bool host_inputs, bool weights) {
   const size_t nn = (size_t)n, mm = (size_t)m;
-  size_t t = align_up(4 * (nn + 1)) + align_up(4 * scan_tmp_words(nn + 1));
+  size_t t = align_up(4 * (nn + 1)) + align_up(4 * scan_tmp_words(nn + 1)) + align_up(4 * ((size_t)RB_BUCKETS + 1)) +
+             align_up(4 * (size_t)RB_BUCKETS);
+  // the bucketed entries of the reverse-CSR build take the place of the
+  // target and weight copies of host inputs, which the layout has consumed
   if (host_inputs) t += align_up(8 * (nn + 1)) + 2 * align_up(std::max<size_t>(4 * mm, 4)) + align_up((nn + 7) / 8);
+  else t += align_up(std::max<size_t>(8 * mm, 8));
+  if (weights) t += align_up(std::max<size_t>(4 * mm, 4));
   return t;
 }
 
@@ -362,6 +373,11 @@ hipError_t upload_game(const eg_game_desc* d, const HostPrep& prep, DevGame& dg,
   uint32_t* scan_tmp = (uint32_t*)sb;
   const size_t scan_words = scan_tmp_words(nn + 1);
   sb += align_up(4 * scan_words);
+  RcsrScratch rx{};
+  rx.bcnt = (uint32_t*)sb;
+  sb += align_up(4 * ((size_t)RB_BUCKETS + 1));
+  rx.bcur = (uint32_t*)sb;
+  sb += align_up(4 * (size_t)RB_BUCKETS);
   const int64_t* d_off = d->offsets;
   const int32_t* d_tgt = d->targets;
   const int32_t* d_w = d->weights;
@@ -371,10 +387,12 @@ hipError_t upload_game(const eg_game_desc* d, const HostPrep& prep, DevGame& dg,
     int64_t* o = (int64_t*)sb;
     sb += align_up(8 * (nn + 1));
     int32_t* t = (int32_t*)sb;
+    rx.ent = (int2*)sb;  // written by the reverse-CSR build, after the layout has read t and w
     sb += align_up(std::max<size_t>(4 * mm, 4));
     int32_t* w = (int32_t*)sb;
     sb += align_up(std::max<size_t>(4 * mm, 4));
     uint8_t* ob = (uint8_t*)sb;
+    sb += align_up((nn + 7) / 8);
     if ((r = hipMemcpyAsync(o, d->offsets, 8 * (nn + 1), hipMemcpyHostToDevice, s))) return r;
     if (mm && (r = hipMemcpyAsync(t, d->targets, 4 * mm, hipMemcpyHostToDevice, s))) return r;
     if (mm && (r = hipMemcpyAsync(w, d->weights, 4 * mm, hipMemcpyHostToDevice, s))) return r;
@@ -383,7 +401,11 @@ hipError_t upload_game(const eg_game_desc* d, const HostPrep& prep, DevGame& dg,
     d_tgt = t;
     d_w = w;
     d_own = ob;
+  } else {
+    rx.ent = (int2*)sb;
+    sb += align_up(std::max<size_t>(8 * mm, 8));
   }
+  if (dg.rev_w) rx.entw = (int32_t*)sb;
   if ((r = hipMemcpyAsync((void*)dg.act_bits, prep.act_bits.data(), 4 * prep.act_bits.size(),
                           hipMemcpyHostToDevice, s)))
     return r;
@@ -392,7 +414,7 @@ hipError_t upload_game(const eg_game_desc* d, const HostPrep& prep, DevGame& dg,
     return r;
   if (after_layout && (r = hipEventRecord(after_layout, s))) return r;
   if ((r = launch_reverse_csr(dg.rs, dg.edges, d->n, (uint32_t)mm, (uint32_t*)dg.rev_off, (int32_t*)dg.rev_src,
-                              (int32_t*)dg.rev_w, cursor, scan_tmp, scan_words, s)) != hipSuccess)
+                              (int32_t*)dg.rev_w, cursor, scan_tmp, scan_words, rx, s)) != hipSuccess)
     return r;
   if (dg.nparts > 1) return launch_partition(dg, d_own, cursor, scan_tmp, scan_words, s);
   return hipSuccess;
@@ -538,7 +560,7 @@ int eg_create(eg_ctx* ctx, const eg_game_desc* desc, eg_game** out, eg_stats* st
     dg.perm = (const int32_t*)g->perm_mem;
   }
   void* staging = nullptr;
-  if ((e = hipMalloc(&staging, eg::staging_bytes(g->n, g->m, ud.mem == EG_MEM_HOST))) != hipSuccess)
+  if ((e = hipMalloc(&staging, eg::staging_bytes(g->n, g->m, ud.mem == EG_MEM_HOST, filter))) != hipSuccess)
     return cleanup_fail(EG_ENOMEM, "staging allocation", e);
   auto run = [&]() -> hipError_t {
     hipError_t r;
@@ -653,16 +675,34 @@ static int solve_impl(eg_game* g, const eg_solve_opts* opts, int64_t* credits, e
   const eg::DevGame& dg = g->dg;
   const int grid = g->grid;
   const double t0 = now_s();
+  const bool scc = ctx->cfg.scc_schedule != 0;
+  double t_scc = 0;
+  if (scc && !g->scc_mem) {
+    // components and levels of the game graph, once per game
+    HIPCHK(hipMalloc(&g->scc_mem, eg::scc_bytes(g->n)));
+    HIPCHK(hipHostMalloc((void**)&g->h_scc, 8, hipHostMallocDefault));
+    eg::bind_scc(g->scc, g->scc_mem, g->n);
+    const double ts = now_s();
+    HIPCHK(eg::compute_scc(dg, g->scc, g->h_scc, s, &g->scc_info));
+    t_scc = now_s() - ts;
+  }
+  // the level filter of the schedule (cleared again below when it is off)
+  g->dg.level = scc ? g->scc.lev : nullptr;
+  g->dg.cur_level = 0;
   const uint64_t dense_at = std::max<uint64_t>(1, (uint64_t)g->n / (ctx->cfg.dense_div ? ctx->cfg.dense_div : 32));
   const uint64_t small_limit = ctx->cfg.small_limit ? (uint64_t)ctx->cfg.small_limit : eg::SMALL_LIMIT;
   HIPCHK(hipMemsetAsync(dg.ctrl, 0, 4 * eg::C_WORDS, s));
   HIPCHK(hipMemsetAsync(dg.slots, 0, 8 * eg::S_WORDS * (size_t)grid, s));
   HIPCHK(hipEventRecord(g->ev[0], s));
   HIPCHK(eg::launch_init(dg, g->vbits, o.resume ? 1 : 0, grid, s));
+  // component schedule: level 0 replaces the initial active set
+  if (scc) HIPCHK(eg::launch_level_activate(dg, g->scc.lev, 0, 1, grid, s));
   HIPCHK(hipMemcpyAsync(g->h_blk, dg.blk_chg, 4 * (size_t)grid, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   uint64_t active = 0;
   for (int b = 0; b < grid; b++) active += g->h_blk[b];
+  const int32_t nlevels = scc ? (int32_t)g->scc_info.levels : 1;
+  int32_t level = 0;
   uint32_t r = 1;
   uint64_t launched = 0;
   int status = EG_OK;
@@ -686,7 +726,21 @@ static int solve_impl(eg_game* g, const eg_solve_opts* opts, int64_t* credits, e
     eg::bind_seed(g->sb, g->seed_mem, g->n);
   }
   uint64_t next_seed = 0, seeded = 0, seed_passes = 0;  // passes before the first round, then at doubling round counts
-  while (active) {
+  for (;;) {
+    if (!active) {
+      // the active set is empty: the fixpoint, or with the component
+      // schedule the end of a level (the next one starts from its vertices)
+      if (++level >= nlevels) break;
+      g->dg.cur_level = level;
+      HIPCHK(eg::launch_level_activate(dg, g->scc.lev, level, r, grid, s));
+      HIPCHK(hipMemcpyAsync(g->h_blk, dg.blk_chg, 4 * (size_t)grid, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      for (int b = 0; b < grid; b++) active += g->h_blk[b];
+      if (!active) continue;
+      mode = pick(active);
+      if (mode != DENSE) HIPCHK(eg::launch_compact(dg, r, grid, s));
+      batch = 2;
+    }
     if (seeding && launched >= next_seed) {
       HIPCHK(hipEventRecord(g->ev[3], s));
       HIPCHK(eg::launch_seed(dg, g->vbits, g->sb, r, s));
@@ -749,14 +803,17 @@ static int solve_impl(eg_game* g, const eg_solve_opts* opts, int64_t* credits, e
     }
     int next_mode = mode;
     if (mode == DENSE || mode == ALL) {
-      if (g->h_ctrl[eg::C_ANY0 + (r - 1) % 3] == 0) break;  // nothing rose in the last round
+      if (g->h_ctrl[eg::C_ANY0 + (r - 1) % 3] == 0) {  // nothing rose in the last round
+        active = 0;
+        continue;
+      }
       uint64_t changed = 0;
       for (int b = 0; b < grid; b++) changed += g->h_blk[b];
       // predecessors of the changed vertices, at most
       const double est = (double)changed * g->avg_indeg;
       if (mode == ALL) {
         if (est < (double)g->n / 2) next_mode = DENSE;
-      } else if (est >= (double)g->n && dg.nparts == 1) {
+      } else if (est >= (double)g->n && dg.nparts == 1 && !scc) {
         next_mode = ALL;
       } else if (est <= (double)small_limit) {
         next_mode = SMALL;
@@ -765,7 +822,10 @@ static int solve_impl(eg_game* g, const eg_solve_opts* opts, int64_t* credits, e
       }
     } else {
       const uint64_t next = g->h_ctrl[eg::C_CNT0 + r % 3];
-      if (next == 0) break;
+      if (next == 0) {
+        active = 0;
+        continue;
+      }
       next_mode = pick(next);
     }
     if ((max_rounds && launched >= max_rounds) || (budget > 0 && now_s() - t0 > budget) || r > 0xFFFFFF00u) {
@@ -827,6 +887,11 @@ static int solve_impl(eg_game* g, const eg_solve_opts* opts, int64_t* credits, e
     st->dense_rounds = dense_rounds;
     st->all_rounds = all_rounds;
     st->t_seed = t_seed;
+    if (scc) {
+      st->scc_components = g->scc_info.components;
+      st->scc_levels = g->scc_info.levels;
+      st->t_scc = t_scc;
+    }
   }
   if (status != EG_OK) return fail(status, "budget exhausted after %llu rounds", (unsigned long long)launched);
   g->at_fixpoint = true;
@@ -915,6 +980,29 @@ int eg_strategy(eg_game* g, int32_t* choice, double* t_kernel) {
     *t_kernel = ms * 1e-3;
   }
   if (missing) return fail(EG_EDEVICE, "%u player-0 vertices have no witnessing edge", missing);
+  return EG_OK;
+}
+
+int eg_components(eg_game* g, int32_t* comp, int32_t* level, uint32_t* components, uint32_t* levels) {
+  if (!g || !comp || !level) return fail(EG_EINVAL, "null argument");
+  std::lock_guard<std::mutex> lock(g->ctx->solve_mu);
+  HIPCHK(hipSetDevice(g->ctx->cfg.device));
+  hipStream_t s = g->ctx->stream;
+  if (!g->scc_mem) {
+    HIPCHK(hipMalloc(&g->scc_mem, eg::scc_bytes(g->n)));
+    HIPCHK(hipHostMalloc((void**)&g->h_scc, 8, hipHostMallocDefault));
+    eg::bind_scc(g->scc, g->scc_mem, g->n);
+    HIPCHK(eg::compute_scc(g->dg, g->scc, g->h_scc, s, &g->scc_info));
+  }
+  // in the caller's numbering, through the output staging buffer (8n bytes)
+  int32_t* d_comp = (int32_t*)g->out64;
+  int32_t* d_lev = d_comp + g->n;
+  HIPCHK(eg::launch_scc_output(g->dg, g->scc, d_comp, d_lev, s));
+  HIPCHK(hipMemcpyAsync(comp, d_comp, 4 * (size_t)g->n, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(level, d_lev, 4 * (size_t)g->n, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (components) *components = g->scc_info.components;
+  if (levels) *levels = g->scc_info.levels;
   return EG_OK;
 }
 

@@ -70,6 +70,10 @@ struct DevGame {
   // a player-1 predecessor p of a changed v joins the next active set only if
   // f(p) < f(v) (-) w(p, v); nullptr: every predecessor joins (Alg. 3)
   const int32_t* rev_w;     // m: weight of the edge of each predecessor entry (stored, clamped)
+  // component schedule: only predecessors on level cur_level join the next
+  // active set (nullptr: no level filter)
+  const int32_t* level;     // n: level of each vertex's component in the condensation
+  int32_t cur_level;
 };
 
 // A game whose edges and values fit in this many bytes may lift small-degree
@@ -95,6 +99,28 @@ struct SeedBuf {
   long long* sum;     // per cycle (indexed by its smallest vertex): total weight
   uint32_t* count;    // 1 word: vertices newly set to TOP
 };
+// Strongly connected components and condensation levels (component schedule).
+struct SccBuf {
+  int32_t* comp;       // n: component label (a vertex id of the component); -1 while unassigned
+  int32_t* lev;        // n: level of the vertex's component (0 = sink components)
+  int32_t* color;      // n: colouring of a phase
+  uint8_t* mark;       // n: reached from the root in a phase
+  uint32_t* flag;      // change counter of a sweep
+  int32_t* max_level;  // next word: the largest level
+};
+struct SccInfo {
+  uint32_t components, levels;
+  uint64_t sweeps, phases;
+};
+size_t scc_bytes(int32_t n);
+void bind_scc(SccBuf& sc, void* base, int32_t n);
+// h_word: pinned host memory of two words.  Synchronises s.
+hipError_t compute_scc(const DevGame& g, const SccBuf& sc, uint32_t* h_word, hipStream_t s, SccInfo* info);
+// comp_out[v], lev_out[v] for caller vertex v (labels are internal vertex ids)
+hipError_t launch_scc_output(const DevGame& g, const SccBuf& sc, int32_t* comp_out, int32_t* lev_out, hipStream_t s);
+// L_r := the vertices of `level` (flags of round parity r), per-block counts in blk_chg
+hipError_t launch_level_activate(const DevGame& g, const int32_t* lev, int32_t level, uint32_t r, int grid,
+                                 hipStream_t s);
 size_t seed_bytes(int32_t n);
 void bind_seed(SeedBuf& sb, void* base, int32_t n);
 hipError_t launch_seed(const DevGame& g, int vbits, const SeedBuf& sb, uint32_t r, hipStream_t s);
@@ -167,8 +193,9 @@ struct HostCopy {
 int host_view(const eg_game_desc* desc, hipStream_t s, HostCopy& hc, eg_game_desc& hd);
 // H2D copy (host descriptor) or device-to-device use (device descriptor), layout,
 // initial-activity flags and predecessor lists into a bound DevGame, on stream s.
-// staging: scratch of staging_bytes(n, m, host) bytes, free once s has completed.
-size_t staging_bytes(int32_t n, int64_t m, bool host_inputs);
+// staging: scratch of staging_bytes(n, m, host, weights) bytes, free once s has
+// completed (weights: room for the reverse weights' build).
+size_t staging_bytes(int32_t n, int64_t m, bool host_inputs, bool weights);
 hipError_t upload_game(const eg_game_desc* d, const HostPrep& prep, DevGame& dg, void* staging, hipStream_t s,
                        hipEvent_t after_layout);
 hipError_t launch_epoch(const BatchTable& bt, int grid, hipStream_t s);
@@ -181,10 +208,19 @@ hipError_t launch_gkey_init(const DevGame& g, int vbits, hipStream_t s);
 hipError_t launch_layout(const int64_t* off, const uint8_t* owner_bits, const int32_t* tgt,
                          const int32_t* w, int32_t n, uint32_t m, int32_t wclamp, uint32_t* rs,
                          int2* edges, hipStream_t s);
+// Scratch of the reverse-CSR build, free once its stream has completed: the
+// entries grouped by bucket of targets and the bucket counters.
+constexpr uint32_t RB_BUCKETS = 4096;  // buckets of targets (at most)
+struct RcsrScratch {
+  int2* ent;       // m: {source, target} per edge, grouped by bucket
+  int32_t* entw;   // m: their weights (needed only when rev_w is built)
+  uint32_t* bcnt;  // RB_BUCKETS + 1: bucket totals, then their exclusive scan
+  uint32_t* bcur;  // RB_BUCKETS: write cursors of the buckets
+};
 // rev_w (nullable): also the weight of each predecessor entry's edge
 hipError_t launch_reverse_csr(const uint32_t* rs, const int2* edges, int32_t n, uint32_t m,
                               uint32_t* rev_off, int32_t* rev_src, int32_t* rev_w, uint32_t* cursor,
-                              uint32_t* scan_tmp, size_t scan_tmp_words, hipStream_t s);
+                              uint32_t* scan_tmp, size_t scan_tmp_words, const RcsrScratch& rx, hipStream_t s);
 size_t scan_tmp_words(size_t count);
 
 // Solve steps

@@ -143,9 +143,49 @@ static hipError_t exclusive_scan(const uint32_t* in, uint32_t* out, size_t count
 }
 
 // ---------------------------------------------------------------- reverse CSR
-__global__ void k_indegree(const int2* edges, uint32_t m, uint32_t* deg) {
-  for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < m; e += gridDim.x * blockDim.x)
-    atomicAdd(&deg[edges[e].x], 1u);
+//
+// The predecessor lists (one entry per edge, grouped by target) are built by
+// two partition passes, so that no counter is shared by the many edges of a
+// hub (in-degrees of power-law games reach 10^5 and more), and every write
+// lands in a short run of consecutive words:
+//  1. by bucket of targets (2^shift consecutive targets, at most RB_BUCKETS
+//     buckets): each block counts the buckets of its chunk of edges in LDS and
+//     adds the non-zero counts to the bucket totals; after a scan of the totals
+//     it counts again, reserves one range per non-empty bucket with one atomic
+//     and writes its entries {source, target} (and weight) there;
+//  2. by target, over the bucketed entries cut into pieces of RP_PIECE: each
+//     piece counts the targets of an LDS window (RP_WIN targets from the base
+//     of its first entry's bucket) and adds the non-zero counts to the
+//     in-degrees; after the scan of the in-degrees (rev_off) it reserves one
+//     range per non-empty target and writes the sources.  The entries of a
+//     piece come from a few consecutive buckets, so the window holds nearly
+//     all of them; an entry outside it takes a global atomic of its own.
+// The order inside a predecessor list is not fixed (it does not matter).
+
+constexpr uint32_t RB_MIN_SHIFT = 10;   // at least 1024 targets per bucket
+constexpr uint32_t RB_CHUNK = 32768;    // edges per block in pass 1
+constexpr uint32_t RB_SUB = 4096;       // edges whose sources one block step resolves
+constexpr uint32_t RP_PIECE = 8192;     // bucketed entries per piece in pass 2
+constexpr uint32_t RP_WIN = 4096;       // targets counted in LDS per piece
+
+uint32_t rb_shift(int32_t n) {
+  uint32_t bits = 0;
+  while (bits < 31 && (1u << bits) < (uint32_t)n) bits++;
+  return bits > 12 + RB_MIN_SHIFT ? bits - 12 : RB_MIN_SHIFT;
+}
+
+// Bucket totals of pass 1.
+__global__ __launch_bounds__(BLOCK) void k_rb_count(const int2* edges, uint32_t m, uint32_t shift, uint32_t* bcnt) {
+  __shared__ uint32_t hist[RB_BUCKETS];
+  const uint32_t tid = threadIdx.x;
+  for (uint32_t i = tid; i < RB_BUCKETS; i += BLOCK) hist[i] = 0;
+  block_sync();
+  const uint32_t e0 = blockIdx.x * RB_CHUNK, e1 = min(m, e0 + RB_CHUNK);
+#pragma unroll 8
+  for (uint32_t e = e0 + tid; e < e1; e += BLOCK) atomicAdd(&hist[(uint32_t)edges[e].x >> shift], 1u);
+  block_sync();
+  for (uint32_t i = tid; i < RB_BUCKETS; i += BLOCK)
+    if (hist[i]) atomicAdd(&bcnt[i], hist[i]);
 }
 
 // source vertex of edge e: the v with rs[v] <= e < rs[v+1] (row starts masked)
@@ -159,20 +199,148 @@ __device__ __forceinline__ int32_t source_of(const uint32_t* rs, int32_t n, uint
   return lo;
 }
 
-// Each thread takes a contiguous run of edges: one binary search finds the
-// source of its first edge, after which the source only moves forward.
-__global__ void k_scatter_preds(const uint32_t* rs, const int2* edges, int32_t n, uint32_t m,
-                                uint32_t chunk, uint32_t* cursor, int32_t* rev_src, int32_t* rev_w) {
-  const uint64_t first = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * chunk;
-  if (first >= m) return;
-  const uint32_t last = (uint32_t)std::min<uint64_t>(m, first + chunk);
-  int32_t v = source_of(rs, n, (uint32_t)first);
-  for (uint32_t e = (uint32_t)first; e < last; e++) {
-    while ((rs[v + 1] & ROW_MASK) <= e) v++;
-    const int2 ed = edges[e];
-    const uint32_t slot = atomicAdd(&cursor[ed.x], 1u);
-    rev_src[slot] = v;
-    if (rev_w) rev_w[slot] = ed.y;
+// source of edge sub + x for x < len, into srcl: the row ids of the row starts
+// inside (sub, sub + len) are written at their positions, the row holding
+// edge sub at position 0, and an inclusive max-scan spreads each row id over
+// its edges (row starts rise with the row id, every row has an edge).
+__device__ __forceinline__ void chunk_sources(const uint32_t* rs, int32_t n, uint32_t sub, uint32_t len,
+                                              uint32_t* srcl, uint32_t* wmax, uint32_t* s_va, uint32_t* s_more) {
+  static_assert(RB_SUB % BLOCK == 0, "whole positions per thread");
+  constexpr uint32_t PER = RB_SUB / BLOCK;
+  const uint32_t tid = threadIdx.x, lane = lane_id(), wid = tid / WAVE;
+  if (tid == 0) *s_va = (uint32_t)source_of(rs, n, sub);
+  for (uint32_t x = tid; x < RB_SUB; x += BLOCK) srcl[x] = 0;
+  block_sync();
+  const uint32_t va = *s_va, s1 = sub + len;
+  for (uint32_t r0 = va + 1, it = 0;; r0 += BLOCK, it++) {
+    const uint32_t r = r0 + tid;
+    bool in = false;
+    if (r < (uint32_t)n) {
+      const uint32_t st = rs[r] & ROW_MASK;  // > sub: row va holds edge sub
+      if (st < s1) {
+        srcl[st - sub] = r;
+        in = true;
+      }
+    }
+    if (tid == BLOCK - 1) s_more[it & 1] = in;  // rows start in increasing order
+    block_sync();
+    if (!s_more[it & 1]) break;
+  }
+  if (tid == 0) srcl[0] = va;
+  block_sync();
+  uint32_t loc[PER];
+  uint32_t run = 0;
+#pragma unroll
+  for (uint32_t j = 0; j < PER; j++) {
+    const uint32_t y = srcl[tid * PER + j];
+    run = y > run ? y : run;
+    loc[j] = run;
+  }
+  uint32_t incl = run;
+#pragma unroll
+  for (int o = 1; o < WAVE; o <<= 1) {
+    const uint32_t y = __shfl_up(incl, o, WAVE);
+    if (lane >= (uint32_t)o) incl = y > incl ? y : incl;
+  }
+  if (lane == WAVE - 1) wmax[wid] = incl;
+  uint32_t excl = __shfl_up(incl, 1, WAVE);
+  if (lane == 0) excl = 0;
+  block_sync();
+  for (uint32_t w = 0; w < wid; w++) excl = wmax[w] > excl ? wmax[w] : excl;
+#pragma unroll
+  for (uint32_t j = 0; j < PER; j++) srcl[tid * PER + j] = loc[j] > excl ? loc[j] : excl;
+  block_sync();
+}
+
+// Pass 1: the block's chunk of edges into the ranges of their buckets.
+__global__ __launch_bounds__(BLOCK) void k_rb_scatter(const uint32_t* rs, const int2* edges, int32_t n, uint32_t m,
+                                                      uint32_t shift, uint32_t* bcur, int2* ent, int32_t* entw) {
+  __shared__ uint32_t base[RB_BUCKETS];  // counts, then the first slot of the block's range per bucket
+  __shared__ uint32_t lcur[RB_BUCKETS];
+  __shared__ uint32_t srcl[RB_SUB];
+  __shared__ uint32_t wmax[BLOCK / WAVE];
+  __shared__ uint32_t s_va, s_more[2];
+  const uint32_t tid = threadIdx.x;
+  for (uint32_t i = tid; i < RB_BUCKETS; i += BLOCK) {
+    base[i] = 0;
+    lcur[i] = 0;
+  }
+  block_sync();
+  const uint32_t e0 = blockIdx.x * RB_CHUNK, e1 = min(m, e0 + RB_CHUNK);
+#pragma unroll 8
+  for (uint32_t e = e0 + tid; e < e1; e += BLOCK) atomicAdd(&base[(uint32_t)edges[e].x >> shift], 1u);
+  block_sync();
+  for (uint32_t i = tid; i < RB_BUCKETS; i += BLOCK)
+    if (base[i]) base[i] = atomicAdd(&bcur[i], base[i]);
+  block_sync();
+  for (uint32_t sub = e0; sub < e1; sub += RB_SUB) {
+    const uint32_t len = min(e1 - sub, RB_SUB);
+    chunk_sources(rs, n, sub, len, srcl, wmax, &s_va, s_more);
+    for (uint32_t x = tid; x < len; x += BLOCK) {
+      const int2 ed = edges[sub + x];
+      const uint32_t b = (uint32_t)ed.x >> shift;
+      const uint32_t slot = base[b] + atomicAdd(&lcur[b], 1u);
+      ent[slot] = make_int2((int32_t)srcl[x], ed.x);
+      if (entw) entw[slot] = ed.y;
+    }
+    block_sync();  // srcl is rewritten by the next step
+  }
+}
+
+// Pass 2, counting: in-degrees.
+__global__ __launch_bounds__(BLOCK) void k_rp_count(const int2* ent, uint32_t m, uint32_t shift, uint32_t* deg) {
+  __shared__ uint32_t hist[RP_WIN];
+  const uint32_t tid = threadIdx.x;
+  for (uint32_t p0 = blockIdx.x * RP_PIECE; p0 < m; p0 += gridDim.x * RP_PIECE) {
+    const uint32_t p1 = min(m, p0 + RP_PIECE);
+    block_sync();  // the previous piece is done with hist
+    for (uint32_t i = tid; i < RP_WIN; i += BLOCK) hist[i] = 0;
+    const uint32_t tmin = ((uint32_t)ent[p0].y >> shift) << shift;
+    block_sync();
+#pragma unroll 8
+    for (uint32_t x = p0 + tid; x < p1; x += BLOCK) {
+      const uint32_t t = (uint32_t)ent[x].y, d = t - tmin;
+      if (d < RP_WIN) atomicAdd(&hist[d], 1u);
+      else atomicAdd(&deg[t], 1u);
+    }
+    block_sync();
+    for (uint32_t i = tid; i < RP_WIN; i += BLOCK)
+      if (hist[i]) atomicAdd(&deg[tmin + i], hist[i]);
+  }
+}
+
+// Pass 2, writing: each piece's sources into the ranges it reserves.
+__global__ __launch_bounds__(BLOCK) void k_rp_scatter(const int2* ent, const int32_t* entw, uint32_t m,
+                                                      uint32_t shift, uint32_t* cursor, int32_t* rev_src,
+                                                      int32_t* rev_w) {
+  __shared__ uint32_t base[RP_WIN];
+  __shared__ uint32_t lcur[RP_WIN];
+  const uint32_t tid = threadIdx.x;
+  for (uint32_t p0 = blockIdx.x * RP_PIECE; p0 < m; p0 += gridDim.x * RP_PIECE) {
+    const uint32_t p1 = min(m, p0 + RP_PIECE);
+    block_sync();
+    for (uint32_t i = tid; i < RP_WIN; i += BLOCK) {
+      base[i] = 0;
+      lcur[i] = 0;
+    }
+    const uint32_t tmin = ((uint32_t)ent[p0].y >> shift) << shift;
+    block_sync();
+#pragma unroll 8
+    for (uint32_t x = p0 + tid; x < p1; x += BLOCK) {
+      const uint32_t d = (uint32_t)ent[x].y - tmin;
+      if (d < RP_WIN) atomicAdd(&base[d], 1u);
+    }
+    block_sync();
+    for (uint32_t i = tid; i < RP_WIN; i += BLOCK)
+      if (base[i]) base[i] = atomicAdd(&cursor[tmin + i], base[i]);
+    block_sync();
+    for (uint32_t x = p0 + tid; x < p1; x += BLOCK) {
+      const int2 en = ent[x];
+      const uint32_t t = (uint32_t)en.y, d = t - tmin;
+      const uint32_t slot = d < RP_WIN ? base[d] + atomicAdd(&lcur[d], 1u) : atomicAdd(&cursor[t], 1u);
+      rev_src[slot] = en.x;
+      if (rev_w) rev_w[slot] = entw[x];
+    }
   }
 }
 
@@ -244,21 +412,34 @@ hipError_t launch_partition(const DevGame& dg, const uint8_t*, uint32_t* cursor,
 
 hipError_t launch_reverse_csr(const uint32_t* rs, const int2* edges, int32_t n, uint32_t m,
                               uint32_t* rev_off, int32_t* rev_src, int32_t* rev_w, uint32_t* cursor,
-                              uint32_t* scan_tmp, size_t scan_tmp_words_avail, hipStream_t s) {
+                              uint32_t* scan_tmp, size_t scan_tmp_words_avail, const RcsrScratch& rx,
+                              hipStream_t s) {
   if (scan_tmp_words_avail < scan_tmp_words((size_t)n + 1)) return hipErrorInvalidValue;
+  const uint32_t shift = rb_shift(n);
+  const uint32_t nb = (((uint32_t)n - 1) >> shift) + 1;
+  if (nb > RB_BUCKETS || (rev_w && !rx.entw)) return hipErrorInvalidValue;
   hipError_t e = hipMemsetAsync(cursor, 0, sizeof(uint32_t) * ((size_t)n + 1), s);
   if (e != hipSuccess) return e;
-  const int grid_e = (int)std::max<int64_t>(1, std::min<int64_t>(((int64_t)m + BLOCK - 1) / BLOCK, 16384));
-  if (m > 0) hipLaunchKernelGGL(k_indegree, dim3(grid_e), dim3(BLOCK), 0, s, edges, m, cursor);
-  e = exclusive_scan(cursor, rev_off, (size_t)n + 1, scan_tmp, s);
-  if (e != hipSuccess) return e;
-  e = hipMemcpyAsync(cursor, rev_off, sizeof(uint32_t) * (size_t)n, hipMemcpyDeviceToDevice, s);
-  if (e != hipSuccess) return e;
   if (m > 0) {
-    const uint32_t chunk = 16;
-    const int grid_s = (int)(((uint64_t)m + (uint64_t)chunk * BLOCK - 1) / ((uint64_t)chunk * BLOCK));
-    hipLaunchKernelGGL(k_scatter_preds, dim3(grid_s), dim3(BLOCK), 0, s, rs, edges, n, m, chunk, cursor,
-                       rev_src, rev_w);
+    if ((e = hipMemsetAsync(rx.bcnt, 0, sizeof(uint32_t) * ((size_t)nb + 1), s)) != hipSuccess) return e;
+    const uint32_t chunks = (m + RB_CHUNK - 1) / RB_CHUNK;
+    hipLaunchKernelGGL(k_rb_count, dim3(chunks), dim3(BLOCK), 0, s, edges, m, shift, rx.bcnt);
+    if ((e = exclusive_scan(rx.bcnt, rx.bcnt, (size_t)nb + 1, scan_tmp, s)) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(rx.bcur, rx.bcnt, sizeof(uint32_t) * nb, hipMemcpyDeviceToDevice, s)) != hipSuccess)
+      return e;
+    hipLaunchKernelGGL(k_rb_scatter, dim3(chunks), dim3(BLOCK), 0, s, rs, edges, n, m, shift, rx.bcur, rx.ent,
+                       rev_w ? rx.entw : (int32_t*)nullptr);
+    const int grid_p = (int)std::min<uint32_t>((m + RP_PIECE - 1) / RP_PIECE, 8192u);
+    hipLaunchKernelGGL(k_rp_count, dim3(grid_p), dim3(BLOCK), 0, s, (const int2*)rx.ent, m, shift, cursor);
+  }
+  if ((e = exclusive_scan(cursor, rev_off, (size_t)n + 1, scan_tmp, s)) != hipSuccess) return e;
+  if (m > 0) {
+    if ((e = hipMemcpyAsync(cursor, rev_off, sizeof(uint32_t) * (size_t)n, hipMemcpyDeviceToDevice, s)) !=
+        hipSuccess)
+      return e;
+    const int grid_p = (int)std::min<uint32_t>((m + RP_PIECE - 1) / RP_PIECE, 8192u);
+    hipLaunchKernelGGL(k_rp_scatter, dim3(grid_p), dim3(BLOCK), 0, s, (const int2*)rx.ent,
+                       (const int32_t*)rx.entw, m, shift, cursor, rev_src, rev_w);
   }
   return hipGetLastError();
 }
@@ -380,6 +561,8 @@ template <bool DENSE, typename V>
 __device__ __forceinline__ void activate(const DevGame& g, RoundShared<V>& sh, bool want, int32_t p,
                                          uint8_t* act_next, int32_t* wl_out, uint32_t* cnt_out,
                                          unsigned long long& pushes) {
+  // component schedule: a predecessor on a higher level waits for its level
+  if (g.level && want && g.level[p] != g.cur_level) want = false;
   if (DENSE) {
     if (want) act_next[p] = 1;  // every writer stores the same value
   } else {
@@ -747,7 +930,8 @@ __device__ __forceinline__ void round_tile(const DevGame& g, RoundShared<V>& sh,
   if (tid == BLOCK - 1) sh.epre[BLOCK] = E;
   sh.ebeg[tid] = raw;
   sh.key[tid] = (raw & OWNER_BIT) ? V(0) : std::numeric_limits<V>::max();
-  if ((DENSE || ALL) && !PART && tid == 0) sh.cbase = contig_base(g, t, E);
+  // every vertex of an all-vertex tile is active: its rows start at thread 0's
+  if ((DENSE || ALL) && !PART && tid == 0) sh.cbase = ALL ? (raw & ROW_MASK) : contig_base(g, t, E);
   if (PART && v >= 0) {
     // the slices' partial keys of v, computed by k_partial
     V k = sh.key[tid];
@@ -892,7 +1076,7 @@ __device__ __forceinline__ void round_seg(const DevGame& g, RoundShared<V>& sh, 
   sh.ebeg[tid] = raw;
   const V ident = (raw & OWNER_BIT) ? V(0) : std::numeric_limits<V>::max();
   sh.key[tid] = ident;
-  if (tid == 0) sh.cbase = contig_base(g, t, E);
+  if (tid == 0) sh.cbase = ALL ? (raw & ROW_MASK) : contig_base(g, t, E);
   block_sync();
   if (E == 0) return;  // block-uniform, and the same in every segment block of the tile
   const uint32_t lo = (uint32_t)((uint64_t)E * seg / nseg), hi = (uint32_t)((uint64_t)E * (seg + 1) / nseg);

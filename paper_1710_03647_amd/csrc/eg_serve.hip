@@ -497,7 +497,8 @@ Server* server_create(const eg_config& cfg, hipStream_t) {
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, cfg.device) != hipSuccess || cus <= 0)
     cus = 256;
-  s->grid = cus * 8;
+  // the epoch kernel's grid: blocks_per_cu resident blocks on every compute unit
+  s->grid = cus * (cfg.blocks_per_cu > 0 ? cfg.blocks_per_cu : 8);
   std::string why;
   s->device_ok = s->init_device(&why);
   if (!s->device_ok) {
@@ -561,7 +562,7 @@ int server_submit(Server* s, const eg_game_desc* desc, hipStream_t stream, eg_ti
   t->m = desc->m;
   t->W = desc->W;
   const size_t nblk = (size_t)std::max<int64_t>(1, std::min<int64_t>(64, ((int64_t)desc->n + TILE_VERTICES - 1) / TILE_VERTICES));
-  size_t scratch = staging_bytes(desc->n, desc->m, true);
+  size_t scratch = staging_bytes(desc->n, desc->m, true, s->cfg.p1_filter != 0);
   if (s->cfg.top_seeding) scratch = std::max(scratch, seed_bytes(desc->n));
   t->footprint = align_up(plan_layout(desc->n, desc->m, t->prep.info.value_bits, nblk, 1, s->cfg.p1_filter != 0).total) +
                  scratch;

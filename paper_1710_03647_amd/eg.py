@@ -28,7 +28,7 @@ ERROR_NAMES = {EG_EINVAL: "EG_EINVAL", EG_ENOMEM: "EG_ENOMEM", EG_EDEVICE: "EG_E
                EG_ECANCELED: "EG_ECANCELED", EG_PENDING: "EG_PENDING"}
 
 EXPORTS = ["eg_ctx_create", "eg_ctx_destroy", "eg_check", "eg_create", "eg_destroy", "eg_solve",
-           "eg_solve_ex", "eg_solve_seeded_noalloc", "eg_set_measure", "eg_strategy", "eg_submit", "eg_poll", "eg_cancel", "eg_wait", "eg_solve_batch",
+           "eg_solve_ex", "eg_solve_seeded_noalloc", "eg_set_measure", "eg_strategy", "eg_components", "eg_submit", "eg_poll", "eg_cancel", "eg_wait", "eg_solve_batch",
            "eg_last_error"]
 
 
@@ -45,7 +45,7 @@ class eg_config(ctypes.Structure):
                 ("time_budget_s", ctypes.c_double), ("max_pending", ctypes.c_int),
                 ("partition", ctypes.c_int), ("blocks_per_cu", ctypes.c_int), ("dense_div", ctypes.c_int),
                 ("small_limit", ctypes.c_int), ("top_seeding", ctypes.c_int), ("seg_edges", ctypes.c_int),
-                ("relabel", ctypes.c_int), ("p1_filter", ctypes.c_int)]
+                ("relabel", ctypes.c_int), ("p1_filter", ctypes.c_int), ("scc_schedule", ctypes.c_int)]
 
 
 class eg_game_desc(ctypes.Structure):
@@ -65,7 +65,8 @@ class eg_stats(ctypes.Structure):
                 ("t_latency", ctypes.c_double), ("launched_rounds", ctypes.c_uint64),
                 ("dense_rounds", ctypes.c_uint64), ("seeded", ctypes.c_uint64), ("seed_passes", ctypes.c_uint64),
                 ("all_rounds", ctypes.c_uint64), ("t_seed", ctypes.c_double),
-                ("filtered_preds", ctypes.c_uint64)]
+                ("filtered_preds", ctypes.c_uint64), ("scc_components", ctypes.c_uint64),
+                ("scc_levels", ctypes.c_uint64), ("t_scc", ctypes.c_double)]
 
     def to_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -114,6 +115,7 @@ def lib():
         L.eg_solve_seeded_noalloc.argtypes = [vp, P(eg_solve_opts), vp, P(eg_stats)]
         L.eg_set_measure.argtypes = [vp, vp]
         L.eg_strategy.argtypes = [vp, vp, P(ctypes.c_double)]
+        L.eg_components.argtypes = [vp, vp, vp, P(ctypes.c_uint32), P(ctypes.c_uint32)]
         L.eg_submit.argtypes = [vp, P(eg_game_desc), P(ctypes.c_uint64)]
         L.eg_poll.argtypes = [vp, ctypes.c_uint64, vp, P(eg_stats)]
         L.eg_cancel.argtypes = [vp, ctypes.c_uint64]
@@ -193,11 +195,11 @@ class Context:
                  bound_mode: int = EG_BOUND_NW, max_rounds: int = 0, time_budget_s: float = 0.0,
                  max_pending: int = 0, partition: int = 0, blocks_per_cu: int = 0, dense_div: int = 0,
                  small_limit: int = 0, top_seeding: int = 0, seg_edges: int = 0, relabel: int = 0,
-                 p1_filter: int = 0):
+                 p1_filter: int = 0, scc_schedule: int = 0):
         handle = getattr(stream, "cuda_stream", stream) or 0
         cfg = eg_config(device, handle, hbm_budget_bytes, max_slots, bound_mode, max_rounds, time_budget_s,
                         max_pending, partition, blocks_per_cu, dense_div, small_limit, int(top_seeding),
-                        seg_edges, relabel, int(p1_filter))
+                        seg_edges, relabel, int(p1_filter), int(scc_schedule))
         p = ctypes.c_void_p()
         rc = lib().eg_ctx_create(ctypes.byref(cfg), ctypes.byref(p))
         if rc != EG_OK:
@@ -330,6 +332,17 @@ class Game:
         if rc != EG_OK:
             raise _err(rc, self.ctx.handle)
         return out, t.value
+
+    def components(self):
+        """Strongly connected components and condensation levels (eg_components).
+        Returns (comp int32[n], level int32[n], number of components, number of levels)."""
+        comp = np.empty(self.n, dtype=np.int32)
+        level = np.empty(self.n, dtype=np.int32)
+        nc, nl = ctypes.c_uint32(0), ctypes.c_uint32(0)
+        rc = lib().eg_components(self.handle, _ptr(comp), _ptr(level), ctypes.byref(nc), ctypes.byref(nl))
+        if rc != EG_OK:
+            raise _err(rc, self.ctx.handle)
+        return comp, level, nc.value, nl.value
 
     def destroy(self):
         if self.handle:

@@ -89,8 +89,10 @@ def test_host_validation_under_asan_ubsan(tmp_path):
                 "-Xarch_host", "-fno-sanitize-recover=all", "-Xarch_host", "-fno-omit-frame-pointer"]
     objs = []
     procs = []
-    for src, extra in (("eg_api.hip", host_san), ("eg_serve.hip", host_san), ("eg_kernels.hip", []),
-                       ("eg_strategy.hip", [])):
+    from paper_1710_03647_amd.build import SOURCES
+
+    for src in SOURCES:
+        extra = host_san if src in ("eg_api.hip", "eg_serve.hip") else []
         obj = str(tmp_path / src.replace(".hip", ".o"))
         procs.append(subprocess.Popen([hipcc, *common, *extra, "-c", os.path.join(csrc, src), "-o", obj],
                                       stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True))
