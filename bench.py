@@ -23,7 +23,10 @@ Also reported (each leg once, after the timed steps, each under a time cap):
                 rest (init, host sync, result copy);
   rmat_lift     full-frontier lift rounds of the same game from its least
                 fixpoint (every vertex lifted, none changes: the lift alone),
-                against the HBM roofline; and player 0's strategy kernel;
+                against the HBM roofline, in place (cut tiles), per-XCD sliced
+                and slice-major; and player 0's strategy kernel;
+  work_options  the same seeded solve with the player-1 frontier filter and
+                with the component schedule: rounds, lifts, time, credits;
   uniform       the uniform random game (n = 2^20, out-degree 16, weights in
                 [-1000, 1000], seed 2): one plain solve to the fixpoint (no
                 seeding) and one seeded solve, credits compared;
@@ -179,16 +182,24 @@ def poisson_run(ctx, synth, games, rate):
     return lat, time.perf_counter() - t0, outs
 
 
-def serving_report(eg, synth, count, budget_bytes):
-    """One-at-a-time vs batched serving on the first `count` stream games; Poisson
-    arrivals at 0.8x the batched closed-loop capacity, and an overload run at
-    1.2x; every game's credits compared alone and in each mix."""
+def serving_report(eg, synth, count):
+    """One-at-a-time vs batched serving on the first `count` stream games, both
+    with TOP seeding; the HBM budget of the server is a quarter of the games'
+    summed footprints (at least the largest one), so admission waits for
+    memory; Poisson arrivals at 0.8x the batched closed-loop capacity, and an
+    overload run at 1.2x; every game's credits compared alone and in each mix."""
     import numpy as np
 
+    from paper_1710_03647_amd import tune
+
     games = [synth.gen_stream_game(i) for i in range(count)]
-    need = sum(eg.check(g)["device_bytes"] for g in games)
+    feet = [eg.check(g)["device_bytes"] for g in games]
+    need = sum(feet)
+    serve_shape = tune.serving_config()
+    # the server's footprint of a game also holds its upload and seeding scratch
+    budget_bytes = max(need // 4, 3 * max(feet))
     alone = []
-    with eg.Context(0) as ctx:
+    with eg.Context(0, top_seeding=1) as ctx:
         t0 = time.perf_counter()
         for g in games:
             with ctx.create(g) as h:
@@ -196,16 +207,20 @@ def serving_report(eg, synth, count, budget_bytes):
         t_one = time.perf_counter() - t0
     log(f"serving: one at a time {count / t_one:.2f} games/s ({t_one:.1f} s)")
     res = {"games": count, "workload": f"first {count} games of the serving stream (seed 5)",
-           "hbm_budget_bytes": budget_bytes, "footprint_sum_bytes": need,
+           "mode": "TOP seeding on, one at a time (eg_solve) and served (eg_submit)",
+           "hbm_budget_bytes": budget_bytes, "footprint_sum_bytes": need, "server_shape": serve_shape,
            "one_at_a_time_games_per_s": count / t_one}
     same = True
-    with eg.Context(0, hbm_budget_bytes=budget_bytes) as ctx:
+    with eg.Context(0, hbm_budget_bytes=budget_bytes, top_seeding=1, **serve_shape) as ctx:
         t0 = time.perf_counter()
         tickets = [ctx.submit(g) for g in games]
+        queued = 0
         for i, (g, t) in enumerate(zip(games, tickets)):
             rc, f, st = ctx.wait(t, g.n)
             same &= bool(np.array_equal(f, alone[i]))
+            queued += st["t_queue"] > 1e-3
         t_cap = time.perf_counter() - t0
+        res["closed_loop_games_waiting_for_admission"] = queued
         cap = count / t_cap
         log(f"serving: batched closed loop {cap:.2f} games/s ({t_cap:.1f} s)")
         rate = 0.8 * cap
@@ -275,7 +290,7 @@ def rmat_lift_leg(eg, game, fstar, stream, base, sweeps):
     roofline; unsliced (the solve's shape) and target-sliced."""
     res = {"workload": "R-MAT scale 22, edge factor 16: full-frontier lift rounds from the least fixpoint (every "
                        "vertex lifted, none changes), int64 values", "n": game.n, "m": game.m}
-    for label, over in (("unsliced", {}), ("sliced", {"partition": 2})):
+    for label, over in (("unsliced", {}), ("sliced", {"partition": 2}), ("slice_major", {"partition": 3})):
         r, strat = lift_sweeps(eg, game, fstar, stream, dict(base, **over), sweeps)
         res[label] = r
         if strat:
@@ -283,6 +298,30 @@ def rmat_lift_leg(eg, game, fstar, stream, base, sweeps):
         log(f"rmat lift ({label}): {r['us_per_round']:.1f} us per round, {r['achieved']:.0f} GB/s = "
             f"{r['frac']:.3f} of peak")
     return res
+
+
+def work_options_leg(eg, game, want, stream, shape):
+    """The options that change the work and never the credits, on the R-MAT
+    game with TOP seeding: the player-1 frontier filter (Alg. 1's predecessor
+    test) and the component schedule (Sec. 6's refinement), each against the
+    plain seeded solve: rounds, lifts, scanned predecessors, device time, and
+    whether the credits are the same."""
+    import numpy as np
+
+    out = {}
+    for label, over in (("seeded", {}), ("p1_filter", {"p1_filter": 1}), ("scc_schedule", {"scc_schedule": 1})):
+        with eg.Context(0, stream=stream, top_seeding=1, **dict(shape, **over)) as ctx:
+            with ctx.create(game) as g:
+                f, st, _ = g.solve()  # the component schedule finds the components here
+                f, st, _ = g.solve()
+        out[label] = {"rounds": st["rounds"], "lifts": st["lifts"], "scanned_preds": st["scanned_preds"],
+                      "filtered_preds": st["filtered_preds"], "t_solve_ms": st["t_solve"] * 1e3,
+                      "identical": bool(np.array_equal(f, want))}
+        if label == "scc_schedule":
+            out[label].update({"components": st["scc_components"], "levels": st["scc_levels"]})
+        log(f"work options ({label}): {st['t_solve'] * 1e3:.2f} ms, {st['rounds']} rounds, {st['lifts']} lifts, "
+            f"identical {out[label]['identical']}")
+    return out
 
 
 def uniform_leg(eg, stream, budget_s):
@@ -351,7 +390,6 @@ def main():
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
-    serve_budget = 4 << 30
     if args.copy_calibration:
         a = torch.empty(1 << 28, dtype=torch.int32, device=dev)  # 1 GiB
         b = torch.empty_like(a)
@@ -363,7 +401,7 @@ def main():
         print("copied 3 x 1 GiB", flush=True)
         return
     if args.serving_only:
-        print(json.dumps({"serving": serving_report(eg, synth, args.serve_games, serve_budget)}), flush=True)
+        print(json.dumps({"serving": serving_report(eg, synth, args.serve_games)}), flush=True)
         return
 
     game, desc = make_game(args.config)
@@ -391,7 +429,9 @@ def main():
     g = ctx.create(game)
     log(f"create: {time.perf_counter() - t0:.2f} s (upload {g.create_stats['t_upload'] * 1e3:.1f} ms, "
         f"reverse CSR {g.create_stats['t_rcsr'] * 1e3:.1f} ms)")
-    out = np.empty(game.n, dtype=np.int64)
+    # pinned host memory for the credits (the caller's choice of buffer: the
+    # device-to-host copy then runs at full PCIe rate)
+    out = torch.empty(game.n, dtype=torch.int64, pin_memory=True).numpy()
     first = None
     partial = bool(args.max_rounds)
 
@@ -478,10 +518,12 @@ def main():
 
     if not partial and args.config == "rmat" and not args.no_rmat_lift and within("rmat_lift", 30):
         line["rmat_lift"] = rmat_lift_leg(eg, game, first, stream, shape, args.rmat_sweeps)
+    if not partial and args.config == "rmat" and args.mode == "seeded" and within("work_options", 30):
+        line["work_options"] = work_options_leg(eg, game, first, stream, shape)
     if not partial and not args.no_uniform and args.config != "uniform" and within("uniform", 150):
         line["uniform"] = uniform_leg(eg, stream, budget_s=100.0)
     if args.serve_games and not partial and within("serving", 120):
-        line["serving"] = serving_report(eg, synth, args.serve_games, serve_budget)
+        line["serving"] = serving_report(eg, synth, args.serve_games)
     if not args.no_cpu_baseline and within("cpu_baseline", 3 * args.cpu_seconds):
         line["cpu_baseline"] = cpu_baseline(game, args.cpu_seconds)
     if skipped:

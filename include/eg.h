@@ -72,9 +72,14 @@ typedef struct {
   uint64_t max_rounds;       /* eg_solve round budget; 0 = none */
   double time_budget_s;      /* eg_solve wall-clock budget; 0 = none */
   int max_pending;           /* serving: queue cap of eg_submit; 0 = 65536 */
-  int partition;             /* dense rounds over target slices (one per XCD), synchronous rounds
-                                that are cheaper but more numerous: 0 or 1 = never, 2 = always
-                                (n <= 2^22) */
+  int partition;             /* dense rounds over a copy of the edges grouped by target slice
+                                (n <= 2^22; 8 bytes per edge more device memory): 0 or 1 = never;
+                                2 = every dense round, one slice per XCD, per-slice partial keys;
+                                3 = slice-major: all-vertex rounds and dense rounds that lift about
+                                half of V or more sweep slices of about 1 MB of f in order, all
+                                blocks at about the same slice, keys held in LDS (the other rounds
+                                stay in place).  Sliced rounds are synchronous: cheaper per round,
+                                possibly more rounds */
   /* launch shape (0 = defaults; set by the autotuner) */
   int blocks_per_cu;         /* resident blocks of 256 threads per compute unit in round kernels: 8 */
   int dense_div;             /* flag sweeps while the active set holds >= n / dense_div vertices: 32 */

@@ -163,6 +163,8 @@ struct eg_game {
   void* perm_mem = nullptr;  // internal id of each caller vertex (renumbered games)
   eg::SeedBuf sb{};
   uint32_t* h_seed = nullptr;
+  void* sl_mem = nullptr;    // slice-major rounds: the blocks' work items
+  int sl_grid = 0;           // k_sliced's grid (the one its work items are balanced over)
   void* scc_mem = nullptr;   // components and levels (component schedule), computed by the first such solve
   uint32_t* h_scc = nullptr;
   eg::SccBuf scc{};
@@ -211,7 +213,7 @@ int eg_ctx_create(const eg_config* cfg, eg_ctx** out) {
     ctx->own_stream = true;
   }
   if (c.blocks_per_cu < 0 || c.blocks_per_cu > 32 || c.dense_div < 0 || c.small_limit < 0 || c.small_limit > 65536 ||
-      c.partition < 0 || c.partition > 2 || c.top_seeding < 0 || c.top_seeding > 1 || c.seg_edges < -1 ||
+      c.partition < 0 || c.partition > 3 || c.top_seeding < 0 || c.top_seeding > 1 || c.seg_edges < -1 ||
       c.p1_filter < 0 || c.p1_filter > 1 || c.scc_schedule < 0 || c.scc_schedule > 1 ||
       c.relabel < 0 || c.relabel > 2 ||
       (c.seg_edges > 0 && c.seg_edges < 256)) {
@@ -261,6 +263,7 @@ static void game_free(eg_game* g) {
   if (g->perm_mem) (void)hipFree(g->perm_mem);
   if (g->h_seed) (void)hipHostFree(g->h_seed);
   if (g->scc_mem) (void)hipFree(g->scc_mem);
+  if (g->sl_mem) (void)hipFree(g->sl_mem);
   if (g->h_scc) (void)hipHostFree(g->h_scc);
   for (auto& e : g->ev)
     if (e) (void)hipEventDestroy(e);
@@ -303,18 +306,27 @@ namespace eg {
 // rounds than with in-place updates, which carry values along paths within a
 // round.  Measured to the fixpoint, unsliced rounds won on every large game
 // tried (uniform 2^20: 66 s against 158 s; R-MAT 2^18: 6.4 s against 21 s).
-uint32_t choose_parts(int32_t n, int64_t, int, int mode) {
-  if (mode == 2 && n <= (1 << PTILE_SHIFT)) return 8;
+uint32_t choose_parts(int32_t n, int64_t, int vbits, int mode) {
+  if (n > (1 << PTILE_SHIFT)) return 1;
+  if (mode == 2) return 8;  // one slice per XCD
+  if (mode == 3) {
+    // slice-major: slices of about SL_SLICE_BYTES of f, 8 to 64 of them
+    const uint64_t bytes = (uint64_t)n * (uint64_t)(vbits / 8);
+    uint32_t s = 8;
+    while (s < 64 && bytes > (uint64_t)s * SL_SLICE_BYTES) s *= 2;
+    return s;
+  }
   return 1;
 }
 
-GameLayout plan_layout(int32_t n, int64_t m, int vbits, size_t nblk, uint32_t nparts, bool filter) {
+GameLayout plan_layout(int32_t n, int64_t m, int vbits, size_t nblk, uint32_t nparts, bool filter, bool slice_major) {
   const size_t nn = (size_t)n, mm = (size_t)m, vb = (size_t)vbits / 8;
   const bool pe = nparts > 1;
   const size_t sizes[L_N] = {4 * (nn + 1), 8 * mm, 4 * (nn + 1), 4 * mm, vb * nn, 2 * align_up(nn + 4), 4 * nn,
                              4 * nn, 8 * nn, 4 * C_WORDS, 8 * S_WORDS, 4 * ((nn + 31) / 32), 4 * nblk,
                              8 * S_WORDS * nblk, pe ? 8 * mm : 0, pe ? 4 * partition_scratch_words(n, nparts) : 0,
-                             pe ? 4 * ((nn + 31) / 32) : 0, pe ? vb * nn * nparts : 0, filter ? 4 * mm : 0};
+                             pe ? 4 * ((nn + 31) / 32) : 0, pe ? vb * nn * (slice_major ? 1 : nparts) : 0,
+                             filter ? 4 * mm : 0};
   GameLayout L{};
   for (int i = 0; i < L_N; i++) {
     L.off[i] = L.total;
@@ -490,6 +502,73 @@ int prepare(const eg_game_desc* desc, int bound_mode, hipStream_t s, HostPrep& p
 
 }  // namespace eg
 
+// Work items of the slice-major rounds (k_sliced): one per tile of PTILE
+// sources, or, for a tile with more than a block's share of the edges, equal
+// parts of its edges; dealt to the blocks largest first, each to the block
+// with the fewest edges so far (every block then sweeps about the same number
+// of edges per slice), and sorted by tile within a block.  The key array is
+// set to the largest key (the rounds keep it so).
+static hipError_t build_slice_major(eg_game* g, hipStream_t s) {
+  eg::DevGame& dg = g->dg;
+  const uint32_t n = (uint32_t)g->n, ntiles = (n + eg::PTILE - 1) / eg::PTILE;
+  std::vector<uint32_t> rs((size_t)n + 1);
+  hipError_t e = hipMemcpyAsync(rs.data(), dg.rs, 4 * ((size_t)n + 1), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return e;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->ctx->cfg.device) != hipSuccess || cus <= 0)
+    cus = 256;
+  const uint32_t grid = (uint32_t)cus * eg::SL_BLOCKS_PER_CU;
+  const uint64_t share = std::max<uint64_t>(4096, ((uint64_t)g->m + grid - 1) / grid);
+  struct Item {
+    uint64_t load;
+    uint32_t tile, word;
+  };
+  std::vector<Item> items;
+  for (uint32_t t = 0; t < ntiles; t++) {
+    const uint32_t a = rs[(size_t)t * eg::PTILE] & eg::ROW_MASK;
+    const uint32_t b = rs[std::min<size_t>(n, (size_t)(t + 1) * eg::PTILE)] & eg::ROW_MASK;
+    const uint64_t edges = b - a;
+    const uint32_t parts = (uint32_t)std::min<uint64_t>(0xFFFF, std::max<uint64_t>(1, (edges + share - 1) / share));
+    for (uint32_t j = 0; j < parts; j++) items.push_back({edges / parts + 1, t, (j << 16) | parts});
+  }
+  std::stable_sort(items.begin(), items.end(), [](const Item& x, const Item& y) { return x.load > y.load; });
+  std::vector<std::vector<Item>> per((size_t)grid);
+  std::vector<std::pair<uint64_t, uint32_t>> heap;  // (load, block), a min-heap
+  for (uint32_t b = 0; b < grid; b++) heap.push_back({0, b});
+  auto cmp = [](const std::pair<uint64_t, uint32_t>& x, const std::pair<uint64_t, uint32_t>& y) { return x > y; };
+  std::make_heap(heap.begin(), heap.end(), cmp);
+  for (const Item& it : items) {
+    std::pop_heap(heap.begin(), heap.end(), cmp);
+    heap.back().first += it.load;
+    per[heap.back().second].push_back(it);
+    std::push_heap(heap.begin(), heap.end(), cmp);
+  }
+  std::vector<uint32_t> begin((size_t)grid + 1, 0);
+  std::vector<uint32_t> flat;  // {tile, part word} pairs
+  for (uint32_t b = 0; b < grid; b++) {
+    auto& v = per[b];
+    std::sort(v.begin(), v.end(), [](const Item& x, const Item& y) { return x.tile < y.tile; });
+    begin[b] = (uint32_t)(flat.size() / 2);
+    for (const Item& it : v) {
+      flat.push_back(it.tile);
+      flat.push_back(it.word);
+    }
+  }
+  begin[grid] = (uint32_t)(flat.size() / 2);
+  auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  const size_t bytes = up(4 * flat.size()) + up(4 * begin.size());
+  if ((e = hipMalloc(&g->sl_mem, bytes)) != hipSuccess) return e;
+  dg.sl_items = (const uint2*)g->sl_mem;
+  dg.sl_begin = (const uint32_t*)((char*)g->sl_mem + up(4 * flat.size()));
+  dg.slice_major = 1;
+  g->sl_grid = (int)grid;
+  if ((e = hipMemcpyAsync((void*)dg.sl_items, flat.data(), 4 * flat.size(), hipMemcpyHostToDevice, s))) return e;
+  if ((e = hipMemcpyAsync((void*)dg.sl_begin, begin.data(), 4 * begin.size(), hipMemcpyHostToDevice, s))) return e;
+  if ((e = eg::launch_fill_max(dg.part, g->n, g->vbits, s))) return e;
+  return hipStreamSynchronize(s);
+}
+
 int eg_create(eg_ctx* ctx, const eg_game_desc* desc, eg_game** out, eg_stats* st) {
   if (!ctx || !desc || !out) return fail(EG_EINVAL, "null argument");
   *out = nullptr;
@@ -519,7 +598,8 @@ int eg_create(eg_ctx* ctx, const eg_game_desc* desc, eg_game** out, eg_stats* st
   g->part_grid = std::max(8, ctx->grid / 8 * 8);
   const uint32_t nparts = eg::choose_parts(g->n, g->m, g->vbits, ctx->cfg.partition);
   const bool filter = ctx->cfg.p1_filter != 0;
-  const eg::GameLayout L = eg::plan_layout(g->n, g->m, g->vbits, nblk, nparts, filter);
+  const bool slice_major = nparts > 1 && ctx->cfg.partition == 3;
+  const eg::GameLayout L = eg::plan_layout(g->n, g->m, g->vbits, nblk, nparts, filter, slice_major);
   hipError_t e = hipMalloc(&g->arena, L.total);
   if (e != hipSuccess) {
     game_free(g);
@@ -572,7 +652,10 @@ int eg_create(eg_ctx* ctx, const eg_game_desc* desc, eg_game** out, eg_stats* st
   e = run();
   (void)hipFree(staging);
   if (e != hipSuccess) return cleanup_fail(EG_EDEVICE, "upload/layout/reverse CSR", e);
-  if (!prep.tile_nseg.empty() && dg.nparts == 1) {
+  if (slice_major) {
+    if ((e = build_slice_major(g, s)) != hipSuccess) return cleanup_fail(EG_EDEVICE, "slice-major work items", e);
+  }
+  if (!prep.tile_nseg.empty() && (dg.nparts == 1 || slice_major)) {
     // edge-balanced dense rounds: one work item per segment of every tile
     const size_t ntiles = prep.tile_nseg.size();
     std::vector<uint32_t> item_tile, item_seg;
@@ -702,6 +785,7 @@ static int solve_impl(eg_game* g, const eg_solve_opts* opts, int64_t* credits, e
   uint64_t active = 0;
   for (int b = 0; b < grid; b++) active += g->h_blk[b];
   const int32_t nlevels = scc ? (int32_t)g->scc_info.levels : 1;
+  bool wide = false;  // slice-major games: the next dense round lifts about half of V or more
   int32_t level = 0;
   uint32_t r = 1;
   uint64_t launched = 0;
@@ -714,6 +798,7 @@ static int solve_impl(eg_game* g, const eg_solve_opts* opts, int64_t* credits, e
   auto pick = [&](uint64_t size) { return size <= small_limit ? SMALL : size >= dense_at ? DENSE : SPARSE; };
   int mode = pick(active);
   if (active && mode != DENSE) HIPCHK(eg::launch_compact(dg, 1, grid, s));
+  wide = 2 * active >= (uint64_t)g->n;
   uint32_t batch = 2;
   double t_kernels = 0;  // device time of the round kernels (back to back within a batch)
   double t_seed = 0;     // device time of the seeding passes
@@ -770,7 +855,10 @@ static int solve_impl(eg_game* g, const eg_solve_opts* opts, int64_t* credits, e
       HIPCHK(eg::launch_rounds_small(dg, g->vbits, r, (uint32_t)allowed, (uint32_t)small_limit, s));
     } else {
       for (uint32_t j = 0; j < allowed; j++, r++) {
-        if (mode == DENSE && dg.nparts > 1) {
+        if (dg.slice_major && (mode == ALL || (mode == DENSE && wide))) {
+          HIPCHK(eg::launch_sliced(dg, g->vbits, r, g->sl_grid, s));
+          HIPCHK(eg::launch_round_parts(dg, g->vbits, r, grid, s, mode == ALL));
+        } else if (mode == DENSE && dg.nparts > 1 && !dg.slice_major) {
           HIPCHK(eg::launch_partial(dg, g->vbits, r, g->part_grid, s));
           HIPCHK(eg::launch_round_parts(dg, g->vbits, r, grid, s));
         } else if ((mode == DENSE || mode == ALL) && dg.nitems) {
@@ -811,9 +899,10 @@ static int solve_impl(eg_game* g, const eg_solve_opts* opts, int64_t* credits, e
       for (int b = 0; b < grid; b++) changed += g->h_blk[b];
       // predecessors of the changed vertices, at most
       const double est = (double)changed * g->avg_indeg;
+      wide = est >= (double)g->n / 2;
       if (mode == ALL) {
         if (est < (double)g->n / 2) next_mode = DENSE;
-      } else if (est >= (double)g->n && dg.nparts == 1 && !scc) {
+      } else if (est >= (double)g->n && (dg.nparts == 1 || dg.slice_major) && !scc) {
         next_mode = ALL;
       } else if (est <= (double)small_limit) {
         next_mode = SMALL;

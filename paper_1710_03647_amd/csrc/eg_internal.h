@@ -55,7 +55,14 @@ struct DevGame {
   const int2* pedges;       // m: {target | tile-local source << 22, weight}, grouped by (tile, slice)
   const uint32_t* poff;     // nchunks + 1: chunk (tile * nparts + slice) starts
   const uint32_t* own_bits; // ceil(n/32): owner bits (1 = player 1)
-  void* part;               // nparts * n keys of width vbits (per-slice partial keys)
+  void* part;               // nparts * n keys of width vbits (per-slice partial keys); slice-major
+                            // rounds: n keys (combined over the slices, reset by the round)
+  // slice-major dense rounds (partition mode 3): each block of k_sliced owns
+  // the work items sl_items[sl_begin[b] .. sl_begin[b+1]) and sweeps the slices
+  // in order for them, holding their keys in LDS (nullptr: not used)
+  uint32_t slice_major;
+  const uint2* sl_items;    // {tile of PTILE sources, part << 16 | parts}: a tile or one part of a cut tile
+  const uint32_t* sl_begin; // grid + 1: each block's first item
   // edge-balanced dense rounds: a tile whose out-degree sum exceeds SEG_EDGES
   // is cut into segments taken by different blocks (nitems = 0: not used)
   uint32_t nitems;          // work items of a dense round: one per segment
@@ -87,6 +94,9 @@ constexpr uint32_t SEG_EDGES = 8192;    // out-edges per segment of a cut tile (
 
 constexpr uint32_t PTILE = 1024;        // vertices per tile of the partitioned copy
 constexpr uint32_t PTILE_SHIFT = 22;    // tile-local source index sits above the 22 target bits
+constexpr uint32_t SL_SLOTS = 4;        // slice-major rounds: tiles whose keys a block holds in LDS at once
+constexpr int SL_BLOCKS_PER_CU = 4;     // resident blocks of k_sliced per compute unit
+constexpr uint32_t SL_SLICE_BYTES = 1u << 20;  // f bytes per target slice (a few slices fit one XCD's L2)
 
 // Scratch of one TOP-seeding pass (device arrays of n entries unless noted).
 struct SeedBuf {
@@ -157,15 +167,21 @@ struct GameLayout {
   size_t total;
 };
 // filter: room for the reverse weights of the player-1 frontier filter
-GameLayout plan_layout(int32_t n, int64_t m, int vbits, size_t nblocks, uint32_t nparts = 1, bool filter = false);
+// slice_major: part holds one key array instead of one per slice
+GameLayout plan_layout(int32_t n, int64_t m, int vbits, size_t nblocks, uint32_t nparts = 1, bool filter = false,
+                       bool slice_major = false);
 void bind_layout(DevGame& dg, char* base, const GameLayout& L, int32_t n, int64_t m, int vbits,
                  uint32_t nparts = 1, bool filter = false);
+// slices of the target-partitioned edge copy for eg_config.partition (1 = none)
 uint32_t choose_parts(int32_t n, int64_t m, int vbits, int mode);
 hipError_t launch_partition(const DevGame& dg, const uint8_t* owner_bits, uint32_t* cursor, uint32_t* scan_tmp,
                             size_t scan_words, hipStream_t s);
 size_t partition_scratch_words(int32_t n, uint32_t nparts);
 hipError_t launch_partial(const DevGame& g, int vbits, uint32_t r, int grid, hipStream_t s);
-hipError_t launch_round_parts(const DevGame& g, int vbits, uint32_t r, int grid, hipStream_t s);
+hipError_t launch_round_parts(const DevGame& g, int vbits, uint32_t r, int grid, hipStream_t s, bool all = false);
+// slice-major rounds: k_sliced on its own grid (the one sl_begin was built for)
+hipError_t launch_sliced(const DevGame& g, int vbits, uint32_t r, int grid, hipStream_t s);
+hipError_t launch_fill_max(void* p, int32_t n, int vbits, hipStream_t s);
 
 // Host-side preparation of a validated game.
 struct HostPrep {
@@ -199,7 +215,8 @@ size_t staging_bytes(int32_t n, int64_t m, bool host_inputs, bool weights);
 hipError_t upload_game(const eg_game_desc* d, const HostPrep& prep, DevGame& dg, void* staging, hipStream_t s,
                        hipEvent_t after_layout);
 hipError_t launch_epoch(const BatchTable& bt, int grid, hipStream_t s);
-hipError_t launch_batch_small(const BatchTable& bt, uint32_t max_rounds, hipStream_t s);
+// budget_ticks: 0, or a time budget per slot in ticks of the 100 MHz realtime counter
+hipError_t launch_batch_small(const BatchTable& bt, uint32_t max_rounds, uint64_t budget_ticks, hipStream_t s);
 hipError_t launch_round_seg(const DevGame& g, int vbits, uint32_t r, int grid, hipStream_t s, bool all);
 hipError_t launch_round_all(const DevGame& g, int vbits, uint32_t r, int grid, hipStream_t s);
 hipError_t launch_gkey_init(const DevGame& g, int vbits, hipStream_t s);

@@ -167,6 +167,13 @@ constexpr uint32_t RB_CHUNK = 32768;    // edges per block in pass 1
 constexpr uint32_t RB_SUB = 4096;       // edges whose sources one block step resolves
 constexpr uint32_t RP_PIECE = 8192;     // bucketed entries per piece in pass 2
 constexpr uint32_t RP_WIN = 4096;       // targets counted in LDS per piece
+constexpr uint32_t RP_BIG = 32768;      // buckets with more entries are written piece by piece
+
+// A bucket written piece by piece (k_rp_scatter) rather than by one block
+// (k_rp_bucket): more than RP_BIG entries, or more targets than LDS holds.
+__device__ __forceinline__ bool rp_big(const uint32_t* bstart, uint32_t b, uint32_t shift) {
+  return (1u << shift) > RP_WIN || bstart[b + 1] - bstart[b] > RP_BIG;
+}
 
 uint32_t rb_shift(int32_t n) {
   uint32_t bits = 0;
@@ -309,10 +316,41 @@ __global__ __launch_bounds__(BLOCK) void k_rp_count(const int2* ent, uint32_t m,
   }
 }
 
-// Pass 2, writing: each piece's sources into the ranges it reserves.
+// Pass 2, writing, buckets of at most RP_BIG entries: one block per bucket.
+// The bucket's entries fill exactly the predecessor lists of its targets, one
+// range of the reverse CSR, which the block writes while its lines are in L2.
+__global__ __launch_bounds__(BLOCK) void k_rp_bucket(const int2* ent, const int32_t* entw, const uint32_t* bstart,
+                                                     uint32_t nb, uint32_t shift, int32_t n, const uint32_t* rev_off,
+                                                     int32_t* rev_src, int32_t* rev_w) {
+  __shared__ uint32_t roff[RP_WIN];
+  __shared__ uint32_t lcur[RP_WIN];
+  const uint32_t tid = threadIdx.x;
+  const uint32_t width = 1u << shift;
+  for (uint32_t b = blockIdx.x; b < nb; b += gridDim.x) {
+    const uint32_t x0 = bstart[b], x1 = bstart[b + 1];
+    if (x1 == x0 || rp_big(bstart, b, shift)) continue;  // block-uniform
+    const uint32_t t0 = b << shift;
+    block_sync();  // the previous bucket is done with the LDS arrays
+    for (uint32_t i = tid; i < width; i += BLOCK) {
+      roff[i] = t0 + i < (uint32_t)n ? rev_off[t0 + i] : 0u;
+      lcur[i] = 0;
+    }
+    block_sync();
+    for (uint32_t x = x0 + tid; x < x1; x += BLOCK) {
+      const int2 en = ent[x];
+      const uint32_t d = (uint32_t)en.y - t0;
+      const uint32_t slot = roff[d] + atomicAdd(&lcur[d], 1u);
+      rev_src[slot] = en.x;
+      if (rev_w) rev_w[slot] = entw[x];
+    }
+  }
+}
+
+// Pass 2, writing, the entries of the other buckets: each piece's sources into
+// the ranges it reserves.
 __global__ __launch_bounds__(BLOCK) void k_rp_scatter(const int2* ent, const int32_t* entw, uint32_t m,
-                                                      uint32_t shift, uint32_t* cursor, int32_t* rev_src,
-                                                      int32_t* rev_w) {
+                                                      uint32_t shift, const uint32_t* bstart, uint32_t* cursor,
+                                                      int32_t* rev_src, int32_t* rev_w) {
   __shared__ uint32_t base[RP_WIN];
   __shared__ uint32_t lcur[RP_WIN];
   const uint32_t tid = threadIdx.x;
@@ -327,8 +365,8 @@ __global__ __launch_bounds__(BLOCK) void k_rp_scatter(const int2* ent, const int
     block_sync();
 #pragma unroll 8
     for (uint32_t x = p0 + tid; x < p1; x += BLOCK) {
-      const uint32_t d = (uint32_t)ent[x].y - tmin;
-      if (d < RP_WIN) atomicAdd(&base[d], 1u);
+      const uint32_t t = (uint32_t)ent[x].y, d = t - tmin;
+      if (d < RP_WIN && rp_big(bstart, t >> shift, shift)) atomicAdd(&base[d], 1u);
     }
     block_sync();
     for (uint32_t i = tid; i < RP_WIN; i += BLOCK)
@@ -337,6 +375,7 @@ __global__ __launch_bounds__(BLOCK) void k_rp_scatter(const int2* ent, const int
     for (uint32_t x = p0 + tid; x < p1; x += BLOCK) {
       const int2 en = ent[x];
       const uint32_t t = (uint32_t)en.y, d = t - tmin;
+      if (!rp_big(bstart, t >> shift, shift)) continue;  // written by k_rp_bucket
       const uint32_t slot = d < RP_WIN ? base[d] + atomicAdd(&lcur[d], 1u) : atomicAdd(&cursor[t], 1u);
       rev_src[slot] = en.x;
       if (rev_w) rev_w[slot] = entw[x];
@@ -438,8 +477,11 @@ hipError_t launch_reverse_csr(const uint32_t* rs, const int2* edges, int32_t n, 
         hipSuccess)
       return e;
     const int grid_p = (int)std::min<uint32_t>((m + RP_PIECE - 1) / RP_PIECE, 8192u);
+    hipLaunchKernelGGL(k_rp_bucket, dim3(std::min<uint32_t>(nb, 4096u)), dim3(BLOCK), 0, s, (const int2*)rx.ent,
+                       (const int32_t*)rx.entw, (const uint32_t*)rx.bcnt, nb, shift, n, (const uint32_t*)rev_off,
+                       rev_src, rev_w);
     hipLaunchKernelGGL(k_rp_scatter, dim3(grid_p), dim3(BLOCK), 0, s, (const int2*)rx.ent,
-                       (const int32_t*)rx.entw, m, shift, cursor, rev_src, rev_w);
+                       (const int32_t*)rx.entw, m, shift, (const uint32_t*)rx.bcnt, cursor, rev_src, rev_w);
   }
   return hipGetLastError();
 }
@@ -933,15 +975,20 @@ __device__ __forceinline__ void round_tile(const DevGame& g, RoundShared<V>& sh,
   // every vertex of an all-vertex tile is active: its rows start at thread 0's
   if ((DENSE || ALL) && !PART && tid == 0) sh.cbase = ALL ? (raw & ROW_MASK) : contig_base(g, t, E);
   if (PART && v >= 0) {
-    // the slices' partial keys of v, computed by k_partial
+    // the slices' partial keys of v, computed by k_partial (one per slice), or
+    // its key combined over the slices by k_sliced
     V k = sh.key[tid];
     const V* part = (const V*)g.part;
-    for (uint32_t q = 0; q < g.nparts; q++) {
+    const uint32_t nk = g.slice_major ? 1u : g.nparts;
+    for (uint32_t q = 0; q < nk; q++) {
       const V y = part[(size_t)q * (uint32_t)g.n + (uint32_t)v];
       k = y < k ? y : k;
     }
     sh.key[tid] = k;
   }
+  // slice-major: every key is reset for the next round (a larger key is the
+  // identity of the min for both players: every vertex has an out-edge)
+  if (PART && g.slice_major && idx < items) ((V*)g.part)[idx] = std::numeric_limits<V>::max();
   block_sync();
   if (E == 0) return;  // block-uniform: no active vertex in this tile
 
@@ -1244,6 +1291,109 @@ __global__ __launch_bounds__(BLOCK) void k_partial(DevGame g, uint32_t r) {
   }
 }
 
+// Slice-major dense round, first kernel (partition mode 3).  The edge copy is
+// grouped by (tile of PTILE sources, target slice), with slices of about
+// SL_SLICE_BYTES of f.  Every block owns the work items sl_items[sl_begin[b]
+// .. sl_begin[b+1]) (tiles, or equal parts of the edges of a tile whose edges
+// exceed a block's share), balanced by edges when the game is created, and
+// takes them SL_SLOTS at a time: their keys stay in LDS while the block sweeps
+// the slices in order, so that all blocks gather f from about the same slice
+// at the same time and the gathers hit in L2.  The keys of a group then go to
+// part[]: a plain store for a whole tile, an atomic min for the parts of a cut
+// tile (part[] is reset to the largest key by the combining round, which turns
+// the keys into values: round_tile with PART).  Only f is read, so the keys
+// are those of a synchronous round.
+template <typename V>
+__global__ __launch_bounds__(BLOCK) void k_sliced(DevGame g, uint32_t r) {
+  static_assert(SL_SLOTS * 64 <= BLOCK, "one chunk of the group per thread in the scan");
+  __shared__ V key[SL_SLOTS * PTILE];
+  __shared__ uint32_t own[SL_SLOTS * (PTILE / 32)];
+  __shared__ uint2 s_item[SL_SLOTS];
+  __shared__ uint32_t cpre[BLOCK + 1];  // exclusive prefix of the chunk lengths, slice-major
+  __shared__ uint32_t cbeg[BLOCK];      // first edge of each chunk in the edge copy
+  __shared__ uint32_t wsum[BLOCK / WAVE];
+  if (g.ctrl[C_ANY0 + (r - 1) % 3] == 0) return;  // L_r is empty
+  const V* f = (const V*)g.f;
+  V* part = (V*)g.part;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t n = (uint32_t)g.n, nparts = g.nparts;
+  const uint32_t nwords = (n + 31) / 32;
+  const uint32_t ib = g.sl_begin[blockIdx.x], ie = g.sl_begin[blockIdx.x + 1];
+  for (uint32_t i0 = ib; i0 < ie; i0 += SL_SLOTS) {
+    const uint32_t ni = min(SL_SLOTS, ie - i0);
+    block_sync();  // the previous group's keys have been written out
+    if (tid < ni) s_item[tid] = g.sl_items[i0 + tid];
+    block_sync();
+    for (uint32_t j = tid; j < ni * (PTILE / 32); j += BLOCK) {
+      const uint32_t w = s_item[j / (PTILE / 32)].x * (PTILE / 32) + j % (PTILE / 32);
+      own[j] = w < nwords ? g.own_bits[w] : 0u;
+    }
+    // chunk c = slice * ni + slot of the group: its edge range in the copy
+    const uint32_t nch = nparts * ni;
+    uint32_t len = 0;
+    if (tid < nch) {
+      const uint2 it = s_item[tid % ni];
+      const uint32_t c = it.x * nparts + tid / ni;
+      const uint32_t a = g.poff[c], b = g.poff[c + 1];
+      const uint32_t pj = it.y >> 16, pc = it.y & 0xFFFFu;
+      const uint32_t lo = a + (uint32_t)((uint64_t)(b - a) * pj / pc);
+      const uint32_t hi = a + (uint32_t)((uint64_t)(b - a) * (pj + 1) / pc);
+      cbeg[tid] = lo;
+      len = hi - lo;
+    }
+    uint32_t total;
+    const uint32_t ex = block_excl_scan(len, wsum, &total);  // its barrier also publishes own and cbeg
+    cpre[tid] = ex;
+    if (tid == BLOCK - 1) cpre[BLOCK] = total;
+    for (uint32_t j = tid; j < ni * PTILE; j += BLOCK)
+      key[j] = ((own[j >> 5] >> (j & 31)) & 1u) ? V(0) : std::numeric_limits<V>::max();
+    block_sync();
+    // The group's chunks as one range of `total` edges, slice by slice: every
+    // step keeps UNROLL * BLOCK edges in flight and moves through the slices
+    // in order.  Each lane walks its own chunk cursor forward (its positions
+    // only grow).
+    uint32_t cur = 0;
+    for (uint32_t x0 = 0; x0 < total; x0 += BLOCK * UNROLL) {
+      int2 ed[UNROLL];
+      uint32_t slot[UNROLL];
+#pragma unroll
+      for (int jj = 0; jj < UNROLL; jj++) {
+        const uint32_t x = x0 + jj * BLOCK + tid;
+        const uint32_t xc = x < total ? x : total - 1;
+        while (cpre[cur + 1] <= xc) cur++;
+        slot[jj] = cur % ni;
+        ed[jj] = g.pedges[cbeg[cur] + (xc - cpre[cur])];
+      }
+      V fu[UNROLL];
+#pragma unroll
+      for (int jj = 0; jj < UNROLL; jj++) fu[jj] = f[(uint32_t)ed[jj].x & ((1u << PTILE_SHIFT) - 1)];
+#pragma unroll
+      for (int jj = 0; jj < UNROLL; jj++) {
+        const uint32_t loc = slot[jj] * PTILE + ((uint32_t)ed[jj].x >> PTILE_SHIFT);
+        V tm = fu[jj] - (V)ed[jj].y;
+        tm = tm > V(0) ? tm : V(0);
+        if (x0 + jj * BLOCK + tid < total)
+          __hip_atomic_fetch_min(&key[loc], ((own[loc >> 5] >> (loc & 31)) & 1u) ? -tm : tm, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+    }
+    block_sync();
+    for (uint32_t j = tid; j < ni * PTILE; j += BLOCK) {
+      const uint2 it = s_item[j / PTILE];
+      const uint32_t v = it.x * PTILE + j % PTILE;
+      if (v >= n) continue;
+      if ((it.y & 0xFFFFu) == 1) part[v] = key[j];
+      else __hip_atomic_fetch_min(part + v, key[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+template <typename V>
+__global__ void k_fill_max(V* p, int32_t n) {
+  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < (uint32_t)n; v += gridDim.x * blockDim.x)
+    p[v] = std::numeric_limits<V>::max();
+}
+
 // Sum the counters of the block into LDS (sh.st must be zero on entry).
 template <typename V>
 __device__ __forceinline__ void block_counters(RoundShared<V>& sh, const Counters& c) {
@@ -1305,15 +1455,20 @@ __global__ __launch_bounds__(BLOCK) void k_round(DevGame g, uint32_t r) {
 // returns the round to run next (k_rounds_small stores it in ctrl[C_NEXT]).
 // All waves of the block share one CU and its caches, so the block barrier
 // orders rounds.
+// deadline (nonzero): also stop before a round that would start after this
+// value of the constant-rate realtime counter (s_memrealtime).
 template <typename V>
 __device__ uint32_t small_rounds(const DevGame& g, RoundShared<V>& sh, uint32_t r0, uint32_t max_rounds,
-                                 uint32_t limit, uint32_t& s_items, int& s_changed, Counters& c) {
+                                 uint32_t limit, uint32_t& s_items, int& s_changed, Counters& c,
+                                 uint64_t deadline = 0) {
   const uint32_t tid = threadIdx.x;
   uint32_t r = r0;
   for (uint32_t k = 0; k < max_rounds; k++, r++) {
     block_sync();
     if (tid == 0) {
-      const uint32_t items = g.ctrl[C_CNT0 + r % 3];
+      uint32_t items = g.ctrl[C_CNT0 + r % 3];
+      // out of time: stop as before an oversized round (nothing is changed)
+      if (deadline && k > 0 && __builtin_amdgcn_s_memrealtime() >= deadline) items = 0xFFFFFFFFu;
       s_items = items;
       s_changed = 0;
       sh.n_push = 0;
@@ -1398,6 +1553,11 @@ __global__ void k_seed_forced(DevGame g, SeedBuf sb) {
 // costs deg / 256 dependent steps instead of deg.
 constexpr uint32_t SEED_SHORT = 32;
 constexpr int SEED_UNROLL = 4;
+// Rows (and predecessor lists) longer than this go to a list and are scanned
+// by a whole block each in a second kernel: the hubs of power-law games sit
+// next to each other after renumbering, and one wave would take them in turn.
+constexpr uint32_t SEED_LONG = 2048;
+constexpr int SEED_LONG_GRID = 1024;
 
 // Candidate order of sigma1: a negative self-loop first (player 1 can stay on
 // it forever, so it is always a certificate), then the largest term, then the
@@ -1412,7 +1572,7 @@ __device__ __forceinline__ bool seed_better(bool lb, V tb, uint32_t kb, bool la,
 // sigma1 for every player-1 vertex over its out-edges into the forced subgraph;
 // the single edge of every player-0 vertex of out-degree 1.
 template <typename V>
-__global__ __launch_bounds__(BLOCK) void k_seed_choose(DevGame g, SeedBuf sb) {
+__global__ __launch_bounds__(BLOCK) void k_seed_choose(DevGame g, SeedBuf sb, int32_t* longs_out) {
   const V* f = (const V*)g.f;
   const uint32_t n = (uint32_t)g.n;
   const uint32_t lane = lane_id();
@@ -1461,7 +1621,10 @@ __global__ __launch_bounds__(BLOCK) void k_seed_choose(DevGame g, SeedBuf sb) {
     } else if (v < n && !p1 && deg == 1) {
       kbest = 0;
     }
-    unsigned long long longs = __ballot(v < n && p1 && deg > SEED_SHORT);
+    // rows longer than SEED_LONG: k_seed_choose_long (their choice stays
+    // "none" here and is written there)
+    wave_append(v < n && p1 && deg > SEED_LONG, (int32_t)v, longs_out, sb.count + 1);
+    unsigned long long longs = __ballot(v < n && p1 && deg > SEED_SHORT && deg <= SEED_LONG);
     while (longs) {
       const uint32_t src = (uint32_t)__ffsll((long long)longs) - 1;
       longs &= longs - 1;
@@ -1527,6 +1690,87 @@ __global__ __launch_bounds__(BLOCK) void k_seed_choose(DevGame g, SeedBuf sb) {
   }
 }
 
+// sigma1 for the player-1 rows listed by k_seed_choose (longer than
+// SEED_LONG): one block per row, SEED_UNROLL * BLOCK edges per step, the
+// same candidate order.
+template <typename V>
+__global__ __launch_bounds__(BLOCK) void k_seed_choose_long(DevGame g, SeedBuf sb, const int32_t* list) {
+  __shared__ int s_l[BLOCK / WAVE];
+  __shared__ V s_t[BLOCK / WAVE];
+  __shared__ uint32_t s_k[BLOCK / WAVE];
+  const V* f = (const V*)g.f;
+  const uint32_t tid = threadIdx.x, lane = lane_id(), wid = tid / WAVE;
+  constexpr uint32_t NONE = 0xFFFFFFFFu;
+  const uint32_t cnt = sb.count[1];
+  for (uint32_t i = blockIdx.x; i < cnt; i += gridDim.x) {
+    const int32_t v = list[i];
+    const uint32_t e0 = g.rs[v] & ROW_MASK, d = (g.rs[v + 1] & ROW_MASK) - e0;
+    bool l = false;
+    V t = -1;
+    uint32_t kk = NONE;
+    for (uint32_t k0 = 0; k0 < d; k0 += SEED_UNROLL * BLOCK) {
+      int2 ed[SEED_UNROLL];
+#pragma unroll
+      for (int j = 0; j < SEED_UNROLL; j++) ed[j] = g.edges[e0 + min(k0 + j * BLOCK + tid, d - 1)];
+      uint8_t fz[SEED_UNROLL];
+      V fu[SEED_UNROLL];
+#pragma unroll
+      for (int j = 0; j < SEED_UNROLL; j++) {
+        fz[j] = sb.forced[ed[j].x];
+        fu[j] = f[ed[j].x];
+      }
+#pragma unroll
+      for (int j = 0; j < SEED_UNROLL; j++) {
+        const uint32_t k = k0 + j * BLOCK + tid;
+        if (k >= d || !fz[j]) continue;
+        const bool lj = ed[j].x == v && ed[j].y < 0;
+        V tm = fu[j] - (V)ed[j].y;
+        tm = tm > V(0) ? tm : V(0);
+        if (kk == NONE || seed_better<V>(lj, tm, k, l, t, kk)) {
+          l = lj;
+          t = tm;
+          kk = k;
+        }
+      }
+    }
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+      const bool lo_ = __shfl_xor((int)l, o, WAVE) != 0;
+      const V to = __shfl_xor(t, o, WAVE);
+      const uint32_t ko = __shfl_xor(kk, o, WAVE);
+      if (ko != NONE && (kk == NONE || seed_better<V>(lo_, to, ko, l, t, kk))) {
+        l = lo_;
+        t = to;
+        kk = ko;
+      }
+    }
+    if (lane == 0) {
+      s_l[wid] = l;
+      s_t[wid] = t;
+      s_k[wid] = kk;
+    }
+    block_sync();
+    if (tid == 0) {
+      for (int w = 1; w < BLOCK / WAVE; w++)
+        if (s_k[w] != NONE && (kk == NONE || seed_better<V>(s_l[w] != 0, s_t[w], s_k[w], l, t, kk))) {
+          l = s_l[w] != 0;
+          t = s_t[w];
+          kk = s_k[w];
+        }
+      int32_t best = -1, bw = 0;
+      if (kk != NONE) {
+        const int2 ed = g.edges[e0 + kk];
+        best = ed.x;
+        bw = ed.y;
+      }
+      sb.succ[v] = best;
+      sb.wgt[v] = bw;
+      sb.p[0][v] = best;
+    }
+    block_sync();  // the next row rewrites the wave results
+  }
+}
+
 __global__ void k_seed_jump(int32_t n, const int32_t* p, const int32_t* lo, int32_t* p2, int32_t* lo2) {
   for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
     const int32_t u = p[v];
@@ -1548,7 +1792,8 @@ __global__ void k_seed_sum(int32_t n, const SeedBuf sb, const int32_t* lo) {
 // TOP on the vertices of negative cycles; their predecessors join L_r (flags).
 // A short predecessor list is flagged by its lane, a long one by the whole wave.
 template <typename V>
-__global__ __launch_bounds__(BLOCK) void k_seed_apply(DevGame g, const SeedBuf sb, const int32_t* lo, uint32_t r) {
+__global__ __launch_bounds__(BLOCK) void k_seed_apply(DevGame g, const SeedBuf sb, const int32_t* lo, uint32_t r,
+                                                      int32_t* longs_out) {
   V* f = (V*)g.f;
   const V top = (V)g.top;
   uint8_t* act = (r & 1) ? g.act1 : g.act0;
@@ -1569,7 +1814,9 @@ __global__ __launch_bounds__(BLOCK) void k_seed_apply(DevGame g, const SeedBuf s
       if (pe - pb <= SEED_SHORT)
         for (uint32_t k = pb; k < pe; k++) act[g.rev_src[k]] = 1;
     }
-    unsigned long long longs = __ballot(set && pe - pb > SEED_SHORT);
+    // lists longer than SEED_LONG: k_seed_apply_long
+    wave_append(set && pe - pb > SEED_LONG, (int32_t)v, longs_out, sb.count + 2);
+    unsigned long long longs = __ballot(set && pe - pb > SEED_SHORT && pe - pb <= SEED_LONG);
     while (longs) {
       const uint32_t src = (uint32_t)__ffsll((long long)longs) - 1;
       longs &= longs - 1;
@@ -1578,6 +1825,19 @@ __global__ __launch_bounds__(BLOCK) void k_seed_apply(DevGame g, const SeedBuf s
     }
   }
   if (mine) atomicAdd(sb.count, mine);
+}
+
+// The predecessors of the TOP vertices listed by k_seed_apply join L_r: one
+// block per list.
+__global__ __launch_bounds__(BLOCK) void k_seed_apply_long(DevGame g, const SeedBuf sb, const int32_t* list,
+                                                           uint32_t r) {
+  uint8_t* act = (r & 1) ? g.act1 : g.act0;
+  const uint32_t cnt = sb.count[2];
+  for (uint32_t i = blockIdx.x; i < cnt; i += gridDim.x) {
+    const int32_t v = list[i];
+    const uint32_t pb = g.rev_off[v], pe = g.rev_off[v + 1];
+    for (uint32_t k = pb + threadIdx.x; k < pe; k += BLOCK) act[g.rev_src[k]] = 1;
+  }
 }
 
 size_t seed_bytes(int32_t n) {
@@ -1609,19 +1869,34 @@ void bind_seed(SeedBuf& sb, void* base, int32_t n) {
 // (ctrl[C_ANY0 + (r - 1) % 3] is set here).
 hipError_t launch_seed(const DevGame& g, int vbits, const SeedBuf& sb, uint32_t r, hipStream_t s) {
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(((int64_t)g.n + BLOCK - 1) / BLOCK, 8192));
-  hipError_t e = hipMemsetAsync(sb.count, 0, 4, s);
+  // count[0]: vertices set to TOP; count[1], count[2]: long rows and long
+  // predecessor lists handed to the block-per-row kernels
+  hipError_t e = hipMemsetAsync(sb.count, 0, 16, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_seed_forced, dim3(grid), dim3(BLOCK), 0, s, g, sb);
-  if (vbits == 32) hipLaunchKernelGGL(k_seed_choose<int32_t>, dim3(grid), dim3(BLOCK), 0, s, g, sb);
-  else hipLaunchKernelGGL(k_seed_choose<int64_t>, dim3(grid), dim3(BLOCK), 0, s, g, sb);
+  // the long-row list lives in p[1] until the first doubling pass writes it
+  if (vbits == 32) {
+    hipLaunchKernelGGL(k_seed_choose<int32_t>, dim3(grid), dim3(BLOCK), 0, s, g, sb, sb.p[1]);
+    hipLaunchKernelGGL(k_seed_choose_long<int32_t>, dim3(SEED_LONG_GRID), dim3(BLOCK), 0, s, g, sb,
+                       (const int32_t*)sb.p[1]);
+  } else {
+    hipLaunchKernelGGL(k_seed_choose<int64_t>, dim3(grid), dim3(BLOCK), 0, s, g, sb, sb.p[1]);
+    hipLaunchKernelGGL(k_seed_choose_long<int64_t>, dim3(SEED_LONG_GRID), dim3(BLOCK), 0, s, g, sb,
+                       (const int32_t*)sb.p[1]);
+  }
   int cur = 0;
   for (int64_t span = 1; span <= 2 * (int64_t)g.n; span *= 2, cur ^= 1)
     hipLaunchKernelGGL(k_seed_jump, dim3(grid), dim3(BLOCK), 0, s, g.n, sb.p[cur], sb.lo[cur], sb.p[cur ^ 1],
                        sb.lo[cur ^ 1]);
   hipLaunchKernelGGL(k_seed_mark, dim3(grid), dim3(BLOCK), 0, s, g.n, sb.p[cur], sb.oncyc);
   hipLaunchKernelGGL(k_seed_sum, dim3(grid), dim3(BLOCK), 0, s, g.n, sb, sb.lo[cur]);
-  if (vbits == 32) hipLaunchKernelGGL(k_seed_apply<int32_t>, dim3(grid), dim3(BLOCK), 0, s, g, sb, sb.lo[cur], r);
-  else hipLaunchKernelGGL(k_seed_apply<int64_t>, dim3(grid), dim3(BLOCK), 0, s, g, sb, sb.lo[cur], r);
+  // the long-list list lives in p[cur ^ 1], free after the last doubling pass
+  if (vbits == 32)
+    hipLaunchKernelGGL(k_seed_apply<int32_t>, dim3(grid), dim3(BLOCK), 0, s, g, sb, sb.lo[cur], r, sb.p[cur ^ 1]);
+  else
+    hipLaunchKernelGGL(k_seed_apply<int64_t>, dim3(grid), dim3(BLOCK), 0, s, g, sb, sb.lo[cur], r, sb.p[cur ^ 1]);
+  hipLaunchKernelGGL(k_seed_apply_long, dim3(SEED_LONG_GRID), dim3(BLOCK), 0, s, g, sb, (const int32_t*)sb.p[cur ^ 1],
+                     r);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   return hipMemsetAsync(g.ctrl + C_ANY0 + (r + 2) % 3, 0xFF, 1, s);
@@ -1754,7 +2029,7 @@ __global__ __launch_bounds__(BLOCK) void k_batch_round(BatchTable bt) {
 // epochs (list longer than small_limit) or kept here.
 template <typename V>
 __device__ void batch_small_slot(const BatchTable& bt, RoundShared<V>& sh, uint32_t s, uint32_t mode,
-                                 uint32_t max_rounds, uint32_t& s_items, int& s_changed) {
+                                 uint32_t max_rounds, uint64_t deadline, uint32_t& s_items, int& s_changed) {
   const DevGame& g = bt.games[s];
   const uint32_t tid = threadIdx.x;
   const uint32_t n = (uint32_t)g.n;
@@ -1777,7 +2052,7 @@ __device__ void batch_small_slot(const BatchTable& bt, RoundShared<V>& sh, uint3
   }
   if (tid < S_WORDS) sh.st[tid] = 0;
   Counters c;
-  r = small_rounds<V>(g, sh, r, max_rounds, bt.small_limit, s_items, s_changed, c);
+  r = small_rounds<V>(g, sh, r, max_rounds, bt.small_limit, s_items, s_changed, c, deadline);
   block_counters(sh, c);
   if (tid < S_WORDS && sh.st[tid]) atomicAdd(&bt.st[s * S_WORDS + tid], sh.st[tid]);
   if (tid == 0) {
@@ -1792,10 +2067,13 @@ __device__ void batch_small_slot(const BatchTable& bt, RoundShared<V>& sh, uint3
   }
 }
 
-__global__ __launch_bounds__(BLOCK) void k_batch_small(BatchTable bt, uint32_t max_rounds) {
+// budget_ticks (nonzero): each slot's rounds stop once this many ticks of the
+// realtime counter have passed since the block started.
+__global__ __launch_bounds__(BLOCK) void k_batch_small(BatchTable bt, uint32_t max_rounds, uint64_t budget_ticks) {
   __shared__ RoundSharedAny sh;
   __shared__ uint32_t s_items, s_mode;
   __shared__ int s_changed;
+  const uint64_t deadline = budget_ticks ? __builtin_amdgcn_s_memrealtime() + budget_ticks : 0;
   for (uint32_t s = blockIdx.x; s < bt.nslots; s += gridDim.x) {
     block_sync();
     if (threadIdx.x == 0) {
@@ -1808,9 +2086,9 @@ __global__ __launch_bounds__(BLOCK) void k_batch_small(BatchTable bt, uint32_t m
     block_sync();
     if (s_mode == BM_DENSE) continue;
     if (bt.games[s].vbits == 32)
-      batch_small_slot<int32_t>(bt, sh.v32, s, s_mode, max_rounds, s_items, s_changed);
+      batch_small_slot<int32_t>(bt, sh.v32, s, s_mode, max_rounds, deadline, s_items, s_changed);
     else
-      batch_small_slot<int64_t>(bt, sh.v64, s, s_mode, max_rounds, s_items, s_changed);
+      batch_small_slot<int64_t>(bt, sh.v64, s, s_mode, max_rounds, deadline, s_items, s_changed);
   }
 }
 
@@ -1820,8 +2098,8 @@ hipError_t launch_epoch(const BatchTable& bt, int grid, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_batch_small(const BatchTable& bt, uint32_t max_rounds, hipStream_t s) {
-  hipLaunchKernelGGL(k_batch_small, dim3(bt.nslots), dim3(BLOCK), 0, s, bt, max_rounds);
+hipError_t launch_batch_small(const BatchTable& bt, uint32_t max_rounds, uint64_t budget_ticks, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_small, dim3(bt.nslots), dim3(BLOCK), 0, s, bt, max_rounds, budget_ticks);
   return hipGetLastError();
 }
 
@@ -1925,9 +2203,27 @@ hipError_t launch_partial(const DevGame& g, int vbits, uint32_t r, int grid, hip
   return hipGetLastError();
 }
 
-hipError_t launch_round_parts(const DevGame& g, int vbits, uint32_t r, int grid, hipStream_t s) {
-  if (vbits == 32) hipLaunchKernelGGL((k_round<int32_t, true, true>), dim3(grid), dim3(BLOCK), 0, s, g, r);
-  else hipLaunchKernelGGL((k_round<int64_t, true, true>), dim3(grid), dim3(BLOCK), 0, s, g, r);
+hipError_t launch_round_parts(const DevGame& g, int vbits, uint32_t r, int grid, hipStream_t s, bool all) {
+  if (vbits == 32) {
+    if (all) hipLaunchKernelGGL((k_round<int32_t, true, true, true>), dim3(grid), dim3(BLOCK), 0, s, g, r);
+    else hipLaunchKernelGGL((k_round<int32_t, true, true>), dim3(grid), dim3(BLOCK), 0, s, g, r);
+  } else {
+    if (all) hipLaunchKernelGGL((k_round<int64_t, true, true, true>), dim3(grid), dim3(BLOCK), 0, s, g, r);
+    else hipLaunchKernelGGL((k_round<int64_t, true, true>), dim3(grid), dim3(BLOCK), 0, s, g, r);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_sliced(const DevGame& g, int vbits, uint32_t r, int grid, hipStream_t s) {
+  if (vbits == 32) hipLaunchKernelGGL(k_sliced<int32_t>, dim3(grid), dim3(BLOCK), 0, s, g, r);
+  else hipLaunchKernelGGL(k_sliced<int64_t>, dim3(grid), dim3(BLOCK), 0, s, g, r);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_max(void* p, int32_t n, int vbits, hipStream_t s) {
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(((int64_t)n + BLOCK - 1) / BLOCK, 8192));
+  if (vbits == 32) hipLaunchKernelGGL(k_fill_max<int32_t>, dim3(grid), dim3(BLOCK), 0, s, (int32_t*)p, n);
+  else hipLaunchKernelGGL(k_fill_max<int64_t>, dim3(grid), dim3(BLOCK), 0, s, (int64_t*)p, n);
   return hipGetLastError();
 }
 

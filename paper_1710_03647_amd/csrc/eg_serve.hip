@@ -172,6 +172,8 @@ struct Server {
   std::map<int, hipGraphExec_t> graphs;
   hipEvent_t ev_upload = nullptr;
   hipEvent_t ev_main = nullptr, ev_side = nullptr;
+  hipEvent_t ev_g0 = nullptr, ev_g1 = nullptr;  // around the epochs' graph (timed)
+  double epoch_us = 0;                           // recent duration of one epoch (0: not measured yet)
 
   bool init_device(std::string* why);
   void release_device();
@@ -199,6 +201,8 @@ bool Server::init_device(std::string* why) {
   if ((e = hipEventCreateWithFlags(&ev_upload, hipEventDisableTiming))) return bad("event", e);
   if ((e = hipEventCreateWithFlags(&ev_main, hipEventDisableTiming))) return bad("event", e);
   if ((e = hipEventCreateWithFlags(&ev_side, hipEventDisableTiming))) return bad("event", e);
+  if ((e = hipEventCreate(&ev_g0))) return bad("event", e);
+  if ((e = hipEventCreate(&ev_g1))) return bad("event", e);
   size_t free_b = 0, total_b = 0;
   if ((e = hipMemGetInfo(&free_b, &total_b))) return bad("hipMemGetInfo", e);
   size_t budget = cfg.hbm_budget_bytes ? cfg.hbm_budget_bytes : free_b / 4;
@@ -258,6 +262,8 @@ void Server::release_device() {
   if (ev_upload) (void)hipEventDestroy(ev_upload);
   if (ev_main) (void)hipEventDestroy(ev_main);
   if (ev_side) (void)hipEventDestroy(ev_side);
+  if (ev_g0) (void)hipEventDestroy(ev_g0);
+  if (ev_g1) (void)hipEventDestroy(ev_g1);
   if (main) (void)hipStreamDestroy(main);
   if (side) (void)hipStreamDestroy(side);
   table_mem = nullptr;
@@ -443,16 +449,33 @@ void Server::run() {
     if (!e) e = hipStreamWaitEvent(side, ev_main, 0);
     if (!e && in_epochs) {
       hipGraphExec_t ex = graph_for(k);
-      e = ex ? hipGraphLaunch(ex, main) : hipErrorUnknown;
+      if (!e) e = hipEventRecord(ev_g0, main);
+      if (!e) e = ex ? hipGraphLaunch(ex, main) : hipErrorUnknown;
+      if (!e) e = hipEventRecord(ev_g1, main);
       epochs += (uint64_t)k;
     }
-    if (!e) e = launch_batch_small(bt, in_epochs ? 8u * (uint32_t)k : 8192u, side);
+    // Games in small mode run beside the epochs for about as long as the
+    // epochs take (a time budget on the device's 100 MHz realtime counter),
+    // so that a game with a long tail of small rounds keeps its pace while
+    // others fill the epochs; alone, 8192 rounds per launch.
+    if (!e) {
+      if (!in_epochs) e = launch_batch_small(bt, 8192u, 0, side);
+      else if (epoch_us > 0) e = launch_batch_small(bt, 1u << 20, (uint64_t)(k * epoch_us * 100.0) + 1, side);
+      else e = launch_batch_small(bt, 8u * (uint32_t)k, 0, side);
+    }
     if (!e) e = hipEventRecord(ev_side, side);
     if (!e) e = hipStreamWaitEvent(main, ev_side, 0);
     if (!e) e = hipMemcpyAsync(h_state, bt.state, 4 * (size_t)nslots, hipMemcpyDeviceToHost, main);
     if (!e) e = hipMemcpyAsync(h_mode, bt.mode, 4 * (size_t)nslots, hipMemcpyDeviceToHost, main);
     if (!e) e = hipMemcpyAsync(h_rounds, bt.rounds, 4 * (size_t)nslots, hipMemcpyDeviceToHost, main);
     if (!e) e = hipStreamSynchronize(main);
+    if (!e && in_epochs) {
+      float ms = 0;
+      if (hipEventElapsedTime(&ms, ev_g0, ev_g1) == hipSuccess && ms > 0) {
+        const double us = 1e3 * ms / k;
+        epoch_us = epoch_us > 0 ? 0.75 * epoch_us + 0.25 * us : us;
+      }
+    }
     if (e) {
       std::lock_guard<std::mutex> lock(mu);
       device_error = std::string("batched iteration: ") + hipGetErrorString(e);

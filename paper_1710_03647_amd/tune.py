@@ -15,7 +15,13 @@ keyed by GPU architecture and graph class.  `config_for(game)` returns the
 stored setting, or the library defaults.  The credits never depend on these
 choices; only time does.
 
+The batched server has its own shape (epoch grid, small-mode threshold,
+resident slots), tuned by `tune_serving` on games from the tail of the
+serving stream and returned by `serving_config()`.
+
 Usage: python -m paper_1710_03647_amd.tune uniform   (tunes the uniform game's class)
+       python -m paper_1710_03647_amd.tune rmat --seeded   (times seeded solves of the game itself)
+       python -m paper_1710_03647_amd.tune serving   (tunes the batched server)
 """
 from __future__ import annotations
 
@@ -34,7 +40,7 @@ SPACE = {
     "blocks_per_cu": [4, 8],
     "dense_div": [8, 32],
     "small_limit": [512, 1024, 4096],
-    "partition": [0, 2],
+    "partition": [0, 2, 3],
 }
 
 
@@ -82,30 +88,37 @@ def _proxy(game):
     return game, 2000
 
 
-def _time(game, cfg: dict, max_rounds: int, device: int) -> float:
+def _time(game, cfg: dict, max_rounds: int, device: int, seeded: bool = False) -> float:
     from . import eg
 
-    with eg.Context(device, **cfg) as ctx:
+    with eg.Context(device, top_seeding=int(seeded), **cfg) as ctx:
         with ctx.create(game) as g:
             g.solve(max_rounds=min(max_rounds, 50) if max_rounds else 50, allow_timeout=True)  # warm
-            t0 = time.perf_counter()
-            g.solve(max_rounds=max_rounds, allow_timeout=True)
-            return time.perf_counter() - t0
+            reps = 3 if seeded else 1
+            ts = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                g.solve(max_rounds=max_rounds, allow_timeout=True)
+                ts.append(time.perf_counter() - t0)
+            return sorted(ts)[len(ts) // 2]
 
 
-def tune(game, device: int = 0, path: str = TABLE, space: dict | None = None, verbose: bool = True) -> dict:
-    """Time every candidate on the proxy, store and return the fastest."""
+def tune(game, device: int = 0, path: str = TABLE, space: dict | None = None, verbose: bool = True,
+         seeded: bool = False) -> dict:
+    """Time every candidate on the proxy, store and return the fastest.  With
+    seeded = True the candidates are timed on seeded solves of the game itself
+    (median of three; these take milliseconds where seeding finds the traps)."""
     from . import eg
 
     space = space or SPACE
-    proxy, rounds = _proxy(game)
+    proxy, rounds = (game, 0) if seeded else _proxy(game)
     info = eg.check(game)
     key = f"{arch(device)}:{graph_class(info['n'], info['m'], info['value_bits'])}"
     results = []
     names = list(space)
     for values in itertools.product(*(space[k] for k in names)):
         cfg = dict(zip(names, values))
-        t = _time(proxy, cfg, rounds, device)
+        t = _time(proxy, cfg, rounds, device, seeded)
         results.append((t, cfg))
         if verbose:
             print(f"[tune] {key} {cfg}: {t * 1e3:.1f} ms", file=sys.stderr, flush=True)
@@ -114,7 +127,69 @@ def tune(game, device: int = 0, path: str = TABLE, space: dict | None = None, ve
     table = load_table(path)
     table[key] = {"config": best, "proxy_seconds": best_t,
                   "default_seconds": next((t for t, c in results if all(c[k] == DEFAULTS[k] for k in c)), None),
-                  "proxy": getattr(proxy, "name", ""), "rounds": rounds or "to the fixpoint"}
+                  "proxy": getattr(proxy, "name", ""), "rounds": rounds or "to the fixpoint",
+                  "solve": "seeded" if seeded else "plain"}
+    with open(path, "w") as fh:
+        json.dump(table, fh, indent=1, sort_keys=True)
+    return best
+
+
+# The batched server (eg_submit): blocks of the epoch kernel per compute unit,
+# the frontier size at which a game moves to the single-block small mode, and
+# the number of resident slots.
+SERVE_DEFAULTS = {"blocks_per_cu": 8, "small_limit": 1024, "max_slots": 1024}
+SERVE_SPACE = {"blocks_per_cu": [2, 4, 8], "small_limit": [256, 1024, 4096], "max_slots": [64, 1024]}
+SERVE_KEY = "serving"
+
+
+def serving_config(device: int = 0, path: str = TABLE) -> dict:
+    """Stored launch shape of the batched server (defaults if untuned)."""
+    entry = load_table(path).get(f"{arch(device)}:{SERVE_KEY}")
+    return dict(entry["config"]) if entry else dict(SERVE_DEFAULTS)
+
+
+def _time_serving(games, cfg: dict, budget_bytes: int, device: int) -> float:
+    from . import eg
+
+    with eg.Context(device, hbm_budget_bytes=budget_bytes, top_seeding=1, **cfg) as ctx:
+        rc, _, _ = ctx.wait(ctx.submit(games[0]), games[0].n)  # server thread and graphs up, untimed
+        t0 = time.perf_counter()
+        tickets = [ctx.submit(g) for g in games]
+        for g, t in zip(games, tickets):
+            ctx.wait(t, g.n)
+        return time.perf_counter() - t0
+
+
+def tune_serving(first: int = 4064, count: int = 32, device: int = 0, path: str = TABLE,
+                 space: dict | None = None, verbose: bool = True) -> dict:
+    """Closed-loop time of the batched server (every game submitted at once,
+    every result awaited, TOP seeding on) for each candidate shape, on `count`
+    games of the serving stream from `first` on (the tail of the 4096-game
+    stream, so that the games tuned on are not the ones the benchmark serves).
+    The HBM budget is a quarter of their summed footprints, as in the
+    benchmark.  Stores and returns the fastest shape."""
+    from . import eg, synth
+
+    space = space or SERVE_SPACE
+    games = [synth.gen_stream_game(i) for i in range(first, first + count)]
+    feet = [eg.check(g)["device_bytes"] for g in games]
+    budget = max(sum(feet) // 4, 3 * max(feet))
+    key = f"{arch(device)}:{SERVE_KEY}"
+    results = []
+    names = list(space)
+    for values in itertools.product(*(space[k] for k in names)):
+        cfg = dict(zip(names, values))
+        t = _time_serving(games, cfg, budget, device)
+        results.append((t, cfg))
+        if verbose:
+            print(f"[tune] {key} {cfg}: {count / t:.2f} games/s", file=sys.stderr, flush=True)
+    results.sort(key=lambda x: x[0])
+    best_t, best = results[0]
+    table = load_table(path)
+    table[key] = {"config": best, "games_per_s": count / best_t,
+                  "default_games_per_s": next((count / t for t, c in results
+                                               if all(c[k] == SERVE_DEFAULTS[k] for k in c)), None),
+                  "games": f"serving stream games {first}..{first + count - 1}", "hbm_budget_bytes": budget}
     with open(path, "w") as fh:
         json.dump(table, fh, indent=1, sort_keys=True)
     return best
@@ -125,7 +200,12 @@ if __name__ == "__main__":
     from paper_1710_03647_amd import synth
 
     which = sys.argv[1:] or ["uniform"]
+    seeded = "--seeded" in which
+    which = [w for w in which if w != "--seeded"]
     for w in which:
+        if w == "serving":
+            print(w, tune_serving())
+            continue
         g = {"uniform": synth.gen_uniform_full, "rmat": synth.gen_rmat_full, "plain": synth.gen_plain,
              "torus": lambda: synth.gen_torus(256, seed=4)}[w]()
-        print(w, tune(g))
+        print(w, tune(g, seeded=seeded))

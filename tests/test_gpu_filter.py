@@ -50,6 +50,7 @@ SHAPES = [
     ("uncut", {"seg_edges": -1, "relabel": 1, "blocks_per_cu": 2}),
     ("cut-256", {"seg_edges": 256}),                          # many cut tiles
     ("sliced", {"partition": 2}),
+    ("slice-major", {"partition": 3}),
     ("seeded", {"top_seeding": 1}),
 ]
 

@@ -35,7 +35,8 @@ def test_uniform_full_seeded_equals_plain():
     assert sts["seeded"] > 0 and stp["rounds"] > 1000 * sts["rounds"]
 
 
-@pytest.mark.parametrize("label,over", [("unsliced", {}), ("uncut", {"seg_edges": -1}), ("sliced", {"partition": 2})])
+@pytest.mark.parametrize("label,over", [("unsliced", {}), ("uncut", {"seg_edges": -1}), ("sliced", {"partition": 2}),
+                                        ("slice-major", {"partition": 3})])
 def test_rmat_full_fixpoint_is_stable(label, over):
     game = synth.gen_rmat_full()
     shape = dict(tune.config_for(game), **over)

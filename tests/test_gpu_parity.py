@@ -184,18 +184,21 @@ PARTITIONED = [
 ]
 
 
+@pytest.mark.parametrize("mode", [2, 3], ids=["per-xcd", "slice-major"])
 @pytest.mark.parametrize("name,make", PARTITIONED, ids=[s[0] for s in PARTITIONED])
-def test_partitioned_dense_rounds(oracle_mod, name, make):
-    """Dense rounds over the target-sliced edge copy (forced on small games)."""
+def test_partitioned_dense_rounds(oracle_mod, name, make, mode):
+    """Dense rounds over the target-sliced edge copy (forced on small games):
+    per-XCD slices with partial keys, and slice-major sweeps with keys in LDS."""
     game = make()
-    with eg.Context(0, partition=2) as c:
+    with eg.Context(0, partition=mode) as c:
         f, st = gpu_solve(c, game)
     assert st["dense_rounds"] > 0
     pins.expect_equal(f, oracle_mod.solve(game).f, name)
 
 
+@pytest.mark.parametrize("mode", [2, 3], ids=["per-xcd", "slice-major"])
 @pytest.mark.parametrize("name,make", PARTITIONED[:4], ids=[s[0] for s in PARTITIONED[:4]])
-def test_partitioned_round_is_one_jacobi_step(oracle_mod, name, make):
+def test_partitioned_round_is_one_jacobi_step(oracle_mod, name, make, mode):
     """A partitioned dense round reads only the values of the previous round:
     from any measure below the fixpoint, one resumed round with every vertex
     active is exactly one application of the lifting operator everywhere,
@@ -204,7 +207,7 @@ def test_partitioned_round_is_one_jacobi_step(oracle_mod, name, make):
     want = oracle_mod.solve(game)
     noise = synth.to_int(synth.draws(11, 2, 0, game.n), 0, 4 * game.W)
     f0 = np.minimum(want.f, noise)
-    with eg.Context(0, partition=2) as c:
+    with eg.Context(0, partition=mode) as c:
         g = c.create(game)
         try:
             g.set_measure(f0)
@@ -283,7 +286,7 @@ def test_renumbering_is_invisible(oracle_mod, relabel):
 
 SHAPES = [dict(), dict(blocks_per_cu=4), dict(blocks_per_cu=16, dense_div=4), dict(small_limit=64),
           dict(small_limit=8192, dense_div=256), dict(seg_edges=256), dict(seg_edges=-1, relabel=1),
-          dict(partition=2), dict(relabel=2, seg_edges=512)]
+          dict(partition=2), dict(partition=3), dict(relabel=2, seg_edges=512)]
 
 
 def test_launch_shapes_give_identical_credits(oracle_mod):
