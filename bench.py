@@ -290,7 +290,8 @@ def rmat_lift_leg(eg, game, fstar, stream, base, sweeps):
     roofline; unsliced (the solve's shape) and target-sliced."""
     res = {"workload": "R-MAT scale 22, edge factor 16: full-frontier lift rounds from the least fixpoint (every "
                        "vertex lifted, none changes), int64 values", "n": game.n, "m": game.m}
-    for label, over in (("unsliced", {}), ("sliced", {"partition": 2}), ("slice_major", {"partition": 3})):
+    for label, over in (("unsliced", {}), ("unsliced_no_hub_cache", {"hub_cache": -1}), ("sliced", {"partition": 2}),
+                        ("slice_major", {"partition": 3})):
         r, strat = lift_sweeps(eg, game, fstar, stream, dict(base, **over), sweeps)
         res[label] = r
         if strat:

@@ -113,6 +113,10 @@ typedef struct {
                                 out of the active set until their level starts.  Exact (a level's
                                 successors outside it are already at their least-fixpoint values); the
                                 credits do not change, only the work.  eg_solve only (not serving) */
+  int hub_cache;             /* launch shape: the cut-tile rounds of a game renumbered by in-degree read
+                                the values of its first vertices (the most gathered ones) from a copy
+                                in LDS taken at the start of each round: its size in KB (1 to 64;
+                                0 = 16), or -1 = off */
 } eg_config;
 
 /* A game in CSR form.  Out-edges of v are e in [offsets[v], offsets[v+1]),

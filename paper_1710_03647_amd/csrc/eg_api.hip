@@ -214,7 +214,7 @@ int eg_ctx_create(const eg_config* cfg, eg_ctx** out) {
   }
   if (c.blocks_per_cu < 0 || c.blocks_per_cu > 32 || c.dense_div < 0 || c.small_limit < 0 || c.small_limit > 65536 ||
       c.partition < 0 || c.partition > 3 || c.top_seeding < 0 || c.top_seeding > 1 || c.seg_edges < -1 ||
-      c.p1_filter < 0 || c.p1_filter > 1 || c.scc_schedule < 0 || c.scc_schedule > 1 ||
+      c.p1_filter < 0 || c.p1_filter > 1 || c.scc_schedule < 0 || c.scc_schedule > 1 || c.hub_cache < -1 || c.hub_cache > 64 ||
       c.relabel < 0 || c.relabel > 2 ||
       (c.seg_edges > 0 && c.seg_edges < 256)) {
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
@@ -613,6 +613,11 @@ int eg_create(eg_ctx* ctx, const eg_game_desc* desc, eg_game** out, eg_stats* st
   dg.top = g->bound + prep.clamp + 1;
   dg.lanes_ok = eg::lanes_ok_for(g->n, g->m, g->vbits);
   g->avg_indeg = (double)g->m / (double)nn;
+  // renumbered games: the first ids are the most gathered values
+  if (!prep.perm.empty() && ctx->cfg.hub_cache >= 0) {
+    const size_t bytes = ctx->cfg.hub_cache ? (size_t)ctx->cfg.hub_cache << 10 : eg::HUB_BYTES;
+    dg.hub_n = (uint32_t)std::min<size_t>(nn, bytes / (size_t)(g->vbits / 8));
+  }
 
   auto cleanup_fail = [&](int code, const char* what, hipError_t err) {
     game_free(g);

@@ -81,6 +81,9 @@ struct DevGame {
   // active set (nullptr: no level filter)
   const int32_t* level;     // n: level of each vertex's component in the condensation
   int32_t cur_level;
+  // cut-tile rounds (k_round_seg) read f(0 .. hub_n) from a copy in LDS taken
+  // at the start of the round (0: off); set for games renumbered by in-degree
+  uint32_t hub_n;
 };
 
 // A game whose edges and values fit in this many bytes may lift small-degree
@@ -97,6 +100,7 @@ constexpr uint32_t PTILE_SHIFT = 22;    // tile-local source index sits above th
 constexpr uint32_t SL_SLOTS = 4;        // slice-major rounds: tiles whose keys a block holds in LDS at once
 constexpr int SL_BLOCKS_PER_CU = 4;     // resident blocks of k_sliced per compute unit
 constexpr uint32_t SL_SLICE_BYTES = 1u << 20;  // f bytes per target slice (a few slices fit one XCD's L2)
+constexpr uint32_t HUB_BYTES = 16u << 10;       // default LDS copy of the most gathered values (cut-tile rounds)
 
 // Scratch of one TOP-seeding pass (device arrays of n entries unless noted).
 struct SeedBuf {

@@ -572,17 +572,20 @@ struct RoundShared {
   uint32_t epre[BLOCK + 1];  // exclusive prefix of out-degrees of the tile's active vertices
   uint32_t ebeg[BLOCK];      // their row starts with the owner bit
   V key[BLOCK];              // running min of the per-edge keys (negated terms for player 1)
-  uint32_t ppre[BLOCK + 1];  // exclusive prefix of in-degrees of the tile's changed vertices
-  uint32_t pbeg[BLOCK];      // their predecessor-list starts
-  V pval[BLOCK];             // their new values (player-1 frontier filter)
   uint32_t wsum[BLOCK / WAVE];
   uint32_t wbig[BLOCK / WAVE];  // per wave: some active vertex has more than LANE_DEG out-edges
-  // push stages list entries across the tiles of a sparse round; term is used
-  // only by the contiguous-row lift, which only dense and all-vertex rounds
-  // take, and those never stage entries
+  // The terms of the contiguous-row lift live only during a tile's lift, and
+  // only dense and all-vertex rounds take that lift; the predecessor phase
+  // comes after the lift, and push stages list entries across the tiles of
+  // sparse rounds only.  So the two never overlap in time.
   union {
-    int32_t push[PUSH_CAP];      // sparse: staged entries of L_{r+1}
-    V term[UNROLL * TERM_ROW];   // contiguous-row lift: the terms of one chunk
+    V term[2][UNROLL * TERM_ROW];  // contiguous-row lift: the terms of two consecutive chunks
+    struct {
+      uint32_t ppre[BLOCK + 1];    // exclusive prefix of in-degrees of the tile's changed vertices
+      uint32_t pbeg[BLOCK];        // their predecessor-list starts
+      V pval[BLOCK];               // their new values (player-1 frontier filter)
+      int32_t push[PUSH_CAP];      // sparse: staged entries of L_{r+1}
+    };
   };
   unsigned long long st[S_WORDS];
   uint32_t n_push, base;
@@ -593,6 +596,11 @@ constexpr uint32_t NO_CONTIG = 0xFFFFFFFFu;
 // Reads of data used once per round (plain loads measured faster than
 // non-temporal ones on gfx950 here).
 __device__ __forceinline__ int2 load_edge(const int2* edges, uint32_t e) { return edges[e]; }
+// A streamed edge that should not displace the gathered values from L2.
+__device__ __forceinline__ int2 load_edge_nt(const int2* edges, uint32_t e) {
+  const unsigned long long x = __builtin_nontemporal_load(reinterpret_cast<const unsigned long long*>(edges + e));
+  return make_int2((int32_t)(uint32_t)x, (int32_t)(uint32_t)(x >> 32));
+}
 template <typename T>
 __device__ __forceinline__ T load_stream(const T* p) {
   return *p;
@@ -634,7 +642,7 @@ __device__ __forceinline__ void activate(const DevGame& g, RoundShared<V>& sh, b
 // of a lane overlap instead of each waiting for the one before.
 template <typename V, int J>
 __device__ __forceinline__ void lift_edges(const DevGame& g, RoundShared<V>& sh, const V* f, uint32_t x0,
-                                           uint32_t E) {
+                                           uint32_t E, const V* hub = nullptr, uint32_t hub_n = 0) {
   const uint32_t tid = threadIdx.x;
   uint32_t slot[J];
   bool neg[J];
@@ -651,7 +659,7 @@ __device__ __forceinline__ void lift_edges(const DevGame& g, RoundShared<V>& sh,
   }
   V fu[J];
 #pragma unroll
-  for (int j = 0; j < J; j++) fu[j] = f[ed[j].x];
+  for (int j = 0; j < J; j++) fu[j] = (uint32_t)ed[j].x < hub_n ? hub[ed[j].x] : f[ed[j].x];
   const uint32_t lane = lane_id();
 #pragma unroll
   for (int j = 0; j < J; j++) {
@@ -686,69 +694,132 @@ __device__ __forceinline__ void lift_edges(const DevGame& g, RoundShared<V>& sh,
 // of the current vertex in a register and folds it into the vertex's LDS key
 // (one atomic min per vertex and thread) when the row or the run ends.  Ends
 // with a barrier: the next chunk rewrites the terms.
+// Fold of one chunk of the contiguous-row lift: thread t takes the chunk's
+// positions [x0 + t * UNROLL, + UNROLL) below E, finds the vertex of the first
+// with one search, walks forward across row ends keeping the running key of
+// the current vertex in a register, and folds it into the vertex's LDS key
+// (one atomic min per vertex and thread) when the row or the run ends.
+template <typename V>
+__device__ __forceinline__ void fold_contig(RoundShared<V>& sh, const V* term, uint32_t x0, uint32_t E) {
+  const uint32_t tid = threadIdx.x;
+  const uint32_t a = x0 + tid * UNROLL;
+  if (a >= E) return;
+  uint32_t sl = find_range(sh.epre, a);
+  uint32_t next = sh.epre[sl + 1];
+  bool neg = (sh.ebeg[sl] & OWNER_BIT) != 0;
+  V acc = std::numeric_limits<V>::max();
+#pragma unroll
+  for (int j = 0; j < UNROLL; j++) {
+    const uint32_t x = a + j;
+    if (x < E) {
+      if (x >= next) {  // a row ends inside the run: its vertices have degree >= 1
+        __hip_atomic_fetch_min(&sh.key[sl], acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        do {
+          sl++;
+          next = sh.epre[sl + 1];
+        } while (x >= next);
+        neg = (sh.ebeg[sl] & OWNER_BIT) != 0;
+        acc = std::numeric_limits<V>::max();
+      }
+      const V tm = term[j * TERM_ROW + tid];
+      const V k = neg ? -tm : tm;
+      acc = k < acc ? k : acc;
+    }
+  }
+  __hip_atomic_fetch_min(&sh.key[sl], acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Edges [x0, min(x0 + J * BLOCK, E)) of a tile whose active rows are one
+// contiguous run of edges from `base` (every vertex of the tile active): the
+// edge of position x is edges[base + x], so no search is needed to load it.
+// The block streams the chunk coalesced (lane i takes positions j * BLOCK + i),
+// gathers f of every target with J gathers in flight per lane (the values of
+// the first hub_n vertices from their LDS copy), writes the unsigned terms
+// max(0, f(u) - w) to LDS, and folds them (fold_contig).  Ends with a barrier.
 template <typename V, int J>
 __device__ __forceinline__ void lift_contig(const DevGame& g, RoundShared<V>& sh, const V* f, uint32_t base,
-                                            uint32_t x0, uint32_t E) {
+                                            uint32_t x0, uint32_t E, const V* hub = nullptr, uint32_t hub_n = 0) {
   static_assert(J <= UNROLL, "a chunk holds at most UNROLL * BLOCK terms");
   const uint32_t tid = threadIdx.x;
   int2 ed[J];
 #pragma unroll
   for (int j = 0; j < J; j++) {
     const uint32_t x = x0 + j * BLOCK + tid;
-    ed[j] = load_edge(g.edges, base + (x < E ? x : E - 1));
+    ed[j] = load_edge_nt(g.edges, base + (x < E ? x : E - 1));
   }
   V fu[J];
 #pragma unroll
-  for (int j = 0; j < J; j++) fu[j] = f[ed[j].x];
+  for (int j = 0; j < J; j++) fu[j] = (uint32_t)ed[j].x < hub_n ? hub[ed[j].x] : f[ed[j].x];
 #pragma unroll
   for (int j = 0; j < J; j++) {
     V tm = fu[j] - (V)ed[j].y;
-    sh.term[term_slot(j * BLOCK + tid)] = tm > V(0) ? tm : V(0);
+    sh.term[0][term_slot(j * BLOCK + tid)] = tm > V(0) ? tm : V(0);
   }
   block_sync();
-  const uint32_t a = x0 + tid * UNROLL;  // this thread's positions [a, a + UNROLL) of the chunk
-  if (a < E && tid * UNROLL < (uint32_t)J * BLOCK) {
-    uint32_t sl = find_range(sh.epre, a);
-    uint32_t next = sh.epre[sl + 1];
-    bool neg = (sh.ebeg[sl] & OWNER_BIT) != 0;
-    V acc = std::numeric_limits<V>::max();
-#pragma unroll
-    for (int j = 0; j < UNROLL; j++) {
-      const uint32_t x = a + j;
-      if (x < E) {
-        if (x >= next) {  // a row ends inside the run: its vertices have degree >= 1
-          __hip_atomic_fetch_min(&sh.key[sl], acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-          do {
-            sl++;
-            next = sh.epre[sl + 1];
-          } while (x >= next);
-          neg = (sh.ebeg[sl] & OWNER_BIT) != 0;
-          acc = std::numeric_limits<V>::max();
-        }
-        const V tm = sh.term[j * TERM_ROW + tid];
-        const V k = neg ? -tm : tm;
-        acc = k < acc ? k : acc;
-      }
-    }
-    __hip_atomic_fetch_min(&sh.key[sl], acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-  }
+  fold_contig<V>(sh, sh.term[0], x0, E);
   block_sync();
 }
 
 static_assert(UNROLL == 4, "lift_contig_range dispatches chunk widths 1 to 4");
 
-// Positions [lo, hi) of a contiguous tile, chunk by chunk (block-uniform).
+// Positions [lo, hi) of a contiguous tile (block-uniform).  A range of one
+// chunk goes to lift_contig with as many edges per lane as it needs.  Longer
+// ranges are software-pipelined: the edges of chunk k + 1 are loaded before
+// chunk k's terms are published and its gathers issued before chunk k is
+// folded, the terms of consecutive chunks alternate between the two LDS
+// buffers, and a chunk costs one barrier (the writes of chunk k + 2 into a
+// buffer follow, in every thread, the barrier that follows the fold of chunk
+// k).  Lanes past hi re-read the last edge and their terms are not folded.
 template <typename V>
 __device__ __forceinline__ void lift_contig_range(const DevGame& g, RoundShared<V>& sh, const V* f, uint32_t base,
-                                                  uint32_t lo, uint32_t hi) {
-  for (uint32_t x0 = lo; x0 < hi; x0 += BLOCK * UNROLL) {
-    switch (std::min<uint32_t>((hi - x0 + BLOCK - 1) / BLOCK, UNROLL)) {
-      case 1: lift_contig<V, 1>(g, sh, f, base, x0, hi); break;
-      case 2: lift_contig<V, 2>(g, sh, f, base, x0, hi); break;
-      case 3: lift_contig<V, 3>(g, sh, f, base, x0, hi); break;
-      default: lift_contig<V, UNROLL>(g, sh, f, base, x0, hi); break;
+                                                  uint32_t lo, uint32_t hi, const V* hub = nullptr,
+                                                  uint32_t hub_n = 0) {
+  constexpr uint32_t CH = UNROLL * BLOCK;
+  if (hi <= lo) return;
+  if (hi - lo <= CH) {
+    switch ((hi - lo + BLOCK - 1) / BLOCK) {
+      case 1: lift_contig<V, 1>(g, sh, f, base, lo, hi, hub, hub_n); break;
+      case 2: lift_contig<V, 2>(g, sh, f, base, lo, hi, hub, hub_n); break;
+      case 3: lift_contig<V, 3>(g, sh, f, base, lo, hi, hub, hub_n); break;
+      default: lift_contig<V, UNROLL>(g, sh, f, base, lo, hi, hub, hub_n); break;
     }
+    return;
   }
+  const uint32_t tid = threadIdx.x;
+  int2 ed[UNROLL];
+  V fu[UNROLL];
+#pragma unroll
+  for (int j = 0; j < UNROLL; j++) {
+    const uint32_t x = lo + j * BLOCK + tid;
+    ed[j] = load_edge_nt(g.edges, base + (x < hi ? x : hi - 1));
+  }
+#pragma unroll
+  for (int j = 0; j < UNROLL; j++) fu[j] = (uint32_t)ed[j].x < hub_n ? hub[ed[j].x] : f[ed[j].x];
+  uint32_t buf = 0;
+  for (uint32_t x0 = lo; x0 < hi; x0 += CH, buf ^= 1u) {
+    V* term = sh.term[buf];
+#pragma unroll
+    for (int j = 0; j < UNROLL; j++) {
+      const V tm = fu[j] - (V)ed[j].y;
+      term[term_slot(j * BLOCK + tid)] = tm > V(0) ? tm : V(0);
+    }
+    const uint32_t nx = x0 + CH;
+    const bool more = nx < hi;  // block-uniform
+    if (more) {
+#pragma unroll
+      for (int j = 0; j < UNROLL; j++) {
+        const uint32_t x = nx + j * BLOCK + tid;
+        ed[j] = load_edge_nt(g.edges, base + (x < hi ? x : hi - 1));
+      }
+    }
+    block_sync();  // chunk k's terms are in place
+    if (more) {
+#pragma unroll
+      for (int j = 0; j < UNROLL; j++) fu[j] = (uint32_t)ed[j].x < hub_n ? hub[ed[j].x] : f[ed[j].x];
+    }
+    fold_contig<V>(sh, term, x0, hi);
+  }
+  block_sync();  // the last fold is done
 }
 
 // First edge of the rows of vertex tile t when the active set of a dense round
@@ -1092,7 +1163,8 @@ __device__ __forceinline__ void slice_edges(const DevGame& g, V* key, const uint
 // the flag clearing and the predecessor activation.
 template <typename V, bool ALL = false>
 __device__ __forceinline__ void round_seg(const DevGame& g, RoundShared<V>& sh, uint32_t r, uint32_t t,
-                                          uint32_t seg, uint32_t nseg, Counters& c, uint32_t& s_last) {
+                                          uint32_t seg, uint32_t nseg, Counters& c, uint32_t& s_last,
+                                          const V* hub, uint32_t hub_n) {
   const uint32_t tid = threadIdx.x;
   V* f = (V*)g.f;
   V* gkey = (V*)g.gkey;
@@ -1129,17 +1201,13 @@ __device__ __forceinline__ void round_seg(const DevGame& g, RoundShared<V>& sh, 
   const uint32_t lo = (uint32_t)((uint64_t)E * seg / nseg), hi = (uint32_t)((uint64_t)E * (seg + 1) / nseg);
   const bool contig = !lanes && sh.cbase != NO_CONTIG;
   if (lanes) sh.key[tid] = lift_lanes<V>(g, f, v, raw, deg);
-  if (contig) lift_contig_range<V>(g, sh, f, sh.cbase, lo, hi);
+  if (contig) lift_contig_range<V>(g, sh, f, sh.cbase, lo, hi, hub, hub_n);
   for (uint32_t x0 = lo; x0 < (lanes || contig ? lo : hi); x0 += BLOCK * UNROLL) {
     switch (std::min<uint32_t>((hi - x0 + BLOCK - 1) / BLOCK, UNROLL)) {
-      case 1: lift_edges<V, 1>(g, sh, f, x0, hi); break;
-      case 2: lift_edges<V, 2>(g, sh, f, x0, hi); break;
-      case 3: lift_edges<V, 3>(g, sh, f, x0, hi); break;
-      case 4: lift_edges<V, 4>(g, sh, f, x0, hi); break;
-      case 5: lift_edges<V, 5>(g, sh, f, x0, hi); break;
-      case 6: lift_edges<V, 6>(g, sh, f, x0, hi); break;
-      case 7: lift_edges<V, 7>(g, sh, f, x0, hi); break;
-      default: lift_edges<V, UNROLL>(g, sh, f, x0, hi); break;
+      case 1: lift_edges<V, 1>(g, sh, f, x0, hi, hub, hub_n); break;
+      case 2: lift_edges<V, 2>(g, sh, f, x0, hi, hub, hub_n); break;
+      case 3: lift_edges<V, 3>(g, sh, f, x0, hi, hub, hub_n); break;
+      default: lift_edges<V, UNROLL>(g, sh, f, x0, hi, hub, hub_n); break;
     }
   }
   block_sync();
@@ -1210,6 +1278,12 @@ template <typename V, bool ALL = false>
 __global__ __launch_bounds__(BLOCK) void k_round_seg(DevGame g, uint32_t r) {
   __shared__ RoundShared<V> sh;
   __shared__ uint32_t s_last;
+  // copy of f(0 .. hub_n) in LDS, the most gathered values of a game renumbered
+  // by in-degree (dynamic shared memory of hub_n values; a copy taken at the
+  // start of the round is an earlier value, which the in-place iteration
+  // allows: a change after it re-activates the readers)
+  extern __shared__ __align__(16) unsigned char dyn_lds[];
+  V* hub = reinterpret_cast<V*>(dyn_lds);
   const uint32_t tid = threadIdx.x;
   const uint32_t items = g.ctrl[C_ANY0 + (r - 1) % 3] ? g.nitems : 0u;
   if (blockIdx.x == 0 && tid == 0) {
@@ -1222,11 +1296,16 @@ __global__ __launch_bounds__(BLOCK) void k_round_seg(DevGame g, uint32_t r) {
     return;
   }
   if (tid < S_WORDS) sh.st[tid] = 0;
+  const uint32_t hub_n = g.hub_n;
+  {
+    const V* f = (const V*)g.f;
+    for (uint32_t i = tid; i < hub_n; i += BLOCK) hub[i] = f[i];
+  }
   Counters c;
   for (uint32_t x = blockIdx.x; x < items; x += gridDim.x) {
-    block_sync();  // the previous item is done with the shared arrays
+    block_sync();  // the previous item is done with the shared arrays (and the hub copy is in place)
     const uint32_t t = g.item_tile[x];
-    round_seg<V, ALL>(g, sh, r, t, g.item_seg[x], g.tile_nseg[t], c, s_last);
+    round_seg<V, ALL>(g, sh, r, t, g.item_seg[x], g.tile_nseg[t], c, s_last, hub, hub_n);
   }
   block_counters(sh, c);
   if (tid < S_WORDS) g.slots[blockIdx.x * S_WORDS + tid] += sh.st[tid];
@@ -1362,7 +1441,7 @@ __global__ __launch_bounds__(BLOCK) void k_sliced(DevGame g, uint32_t r) {
         const uint32_t xc = x < total ? x : total - 1;
         while (cpre[cur + 1] <= xc) cur++;
         slot[jj] = cur % ni;
-        ed[jj] = g.pedges[cbeg[cur] + (xc - cpre[cur])];
+        ed[jj] = load_edge_nt(g.pedges, cbeg[cur] + (xc - cpre[cur]));
       }
       V fu[UNROLL];
 #pragma unroll
@@ -2174,12 +2253,13 @@ hipError_t launch_round(const DevGame& g, int vbits, int h, bool dense, uint32_t
 }
 
 hipError_t launch_round_seg(const DevGame& g, int vbits, uint32_t r, int grid, hipStream_t s, bool all) {
+  const size_t hub_bytes = (size_t)g.hub_n * (size_t)(vbits / 8);
   if (vbits == 32) {
-    if (all) hipLaunchKernelGGL((k_round_seg<int32_t, true>), dim3(grid), dim3(BLOCK), 0, s, g, r);
-    else hipLaunchKernelGGL((k_round_seg<int32_t, false>), dim3(grid), dim3(BLOCK), 0, s, g, r);
+    if (all) hipLaunchKernelGGL((k_round_seg<int32_t, true>), dim3(grid), dim3(BLOCK), hub_bytes, s, g, r);
+    else hipLaunchKernelGGL((k_round_seg<int32_t, false>), dim3(grid), dim3(BLOCK), hub_bytes, s, g, r);
   } else {
-    if (all) hipLaunchKernelGGL((k_round_seg<int64_t, true>), dim3(grid), dim3(BLOCK), 0, s, g, r);
-    else hipLaunchKernelGGL((k_round_seg<int64_t, false>), dim3(grid), dim3(BLOCK), 0, s, g, r);
+    if (all) hipLaunchKernelGGL((k_round_seg<int64_t, true>), dim3(grid), dim3(BLOCK), hub_bytes, s, g, r);
+    else hipLaunchKernelGGL((k_round_seg<int64_t, false>), dim3(grid), dim3(BLOCK), hub_bytes, s, g, r);
   }
   return hipGetLastError();
 }

@@ -45,7 +45,8 @@ class eg_config(ctypes.Structure):
                 ("time_budget_s", ctypes.c_double), ("max_pending", ctypes.c_int),
                 ("partition", ctypes.c_int), ("blocks_per_cu", ctypes.c_int), ("dense_div", ctypes.c_int),
                 ("small_limit", ctypes.c_int), ("top_seeding", ctypes.c_int), ("seg_edges", ctypes.c_int),
-                ("relabel", ctypes.c_int), ("p1_filter", ctypes.c_int), ("scc_schedule", ctypes.c_int)]
+                ("relabel", ctypes.c_int), ("p1_filter", ctypes.c_int), ("scc_schedule", ctypes.c_int),
+                ("hub_cache", ctypes.c_int)]
 
 
 class eg_game_desc(ctypes.Structure):
@@ -195,11 +196,11 @@ class Context:
                  bound_mode: int = EG_BOUND_NW, max_rounds: int = 0, time_budget_s: float = 0.0,
                  max_pending: int = 0, partition: int = 0, blocks_per_cu: int = 0, dense_div: int = 0,
                  small_limit: int = 0, top_seeding: int = 0, seg_edges: int = 0, relabel: int = 0,
-                 p1_filter: int = 0, scc_schedule: int = 0):
+                 p1_filter: int = 0, scc_schedule: int = 0, hub_cache: int = 0):
         handle = getattr(stream, "cuda_stream", stream) or 0
         cfg = eg_config(device, handle, hbm_budget_bytes, max_slots, bound_mode, max_rounds, time_budget_s,
                         max_pending, partition, blocks_per_cu, dense_div, small_limit, int(top_seeding),
-                        seg_edges, relabel, int(p1_filter), int(scc_schedule))
+                        seg_edges, relabel, int(p1_filter), int(scc_schedule), int(hub_cache))
         p = ctypes.c_void_p()
         rc = lib().eg_ctx_create(ctypes.byref(cfg), ctypes.byref(p))
         if rc != EG_OK:

@@ -35,7 +35,8 @@ import time
 PKG = os.path.dirname(os.path.abspath(__file__))
 TABLE = os.path.join(PKG, "tuning.json")
 
-DEFAULTS = {"blocks_per_cu": 8, "dense_div": 32, "small_limit": 1024, "partition": 0, "seg_edges": 0, "relabel": 0}
+DEFAULTS = {"blocks_per_cu": 8, "dense_div": 32, "small_limit": 1024, "partition": 0, "seg_edges": 0, "relabel": 0,
+            "hub_cache": 0}
 SPACE = {
     "blocks_per_cu": [4, 8],
     "dense_div": [8, 32],
