@@ -1172,8 +1172,21 @@ __device__ __forceinline__ void round_seg(const DevGame& g, RoundShared<V>& sh, 
   uint8_t* act_cur = (r & 1) ? g.act1 : g.act0;
   uint8_t* act_next = (r & 1) ? g.act0 : g.act1;
   const uint32_t idx = t * TILE + tid;
-  int32_t v = -1;
-  if (idx < (uint32_t)g.n && (ALL || act_cur[idx])) v = (int32_t)idx;
+  const bool in = idx < (uint32_t)g.n;
+  const bool was_active = in && (ALL || act_cur[idx]);
+  // A tile with at least half of its vertices active lifts all of them: its
+  // rows are then one contiguous run of edges (the cheaper contiguous-row
+  // lift), and lifting a vertex whose successors did not change returns its
+  // value, so the extra lifts are exact.  Only the active ones are counted as
+  // work (lifts, relaxed edges).  Every segment block of a cut tile reads the
+  // same flags (the tile's last block clears them), so all decide alike.
+  bool lifted = was_active;
+  if (!ALL) {
+    const uint32_t nact = (uint32_t)__syncthreads_count(was_active);
+    const uint32_t nin = min((uint32_t)TILE, (uint32_t)g.n - t * TILE);
+    if (2 * nact >= nin) lifted = in;
+  }
+  int32_t v = lifted ? (int32_t)idx : -1;
   uint32_t raw = 0, deg = 0, pb = 0, pe = 0;
   V old = 0;
   if (v >= 0) {
@@ -1241,8 +1254,10 @@ __device__ __forceinline__ void round_seg(const DevGame& g, RoundShared<V>& sh, 
     V nv = (raw & OWNER_BIT) ? -k : k;
     if (nv > bound) nv = top;
     if (nv < old) nv = old;  // writes never lower a value (see round_tile)
-    c.lifts++;
-    c.edges += deg;
+    if (was_active) {
+      c.lifts++;
+      c.edges += deg;
+    }
     if (nv != old) {
       f[v] = nv;
       nval = nv;

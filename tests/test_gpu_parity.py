@@ -286,12 +286,14 @@ def test_renumbering_is_invisible(oracle_mod, relabel):
 
 SHAPES = [dict(), dict(blocks_per_cu=4), dict(blocks_per_cu=16, dense_div=4), dict(small_limit=64),
           dict(small_limit=8192, dense_div=256), dict(seg_edges=256), dict(seg_edges=-1, relabel=1),
-          dict(partition=2), dict(partition=3), dict(relabel=2, seg_edges=512)]
+          dict(partition=2), dict(partition=3), dict(relabel=2, seg_edges=512),
+          dict(relabel=2, seg_edges=512, hub_cache=1), dict(relabel=2, hub_cache=-1), dict(relabel=2, hub_cache=40)]
 
 
 def test_launch_shapes_give_identical_credits(oracle_mod):
     """The credits do not depend on the launch shape: occupancy, representation
-    thresholds, tile cutting, renumbering and slicing (bit-identical results)."""
+    thresholds, tile cutting, renumbering, slicing and the LDS copy of the most
+    gathered values (bit-identical results)."""
     for game in (synth.gen_rmat(13, 16, seed=7), synth.gen_uniform(9999, 7, 80, 29)):
         want = oracle_mod.solve(game).f
         for shape in SHAPES:
