@@ -30,12 +30,14 @@ Also reported (each leg once, after the timed steps, each under a time cap):
   uniform       the uniform random game (n = 2^20, out-degree 16, weights in
                 [-1000, 1000], seed 2): one plain solve to the fixpoint (no
                 seeding) and one seeded solve, credits compared;
-  serving       the first --serve-games games of the serving stream (n
+  serving       the first --serve-games (128) games of the serving stream (n
                 log-uniform in [1e3, 1e5], out-degree U{2..16}, W log-uniform in
-                [10, 1000]): one-game-at-a-time solves, the batched server's
-                closed-loop capacity, Poisson arrivals at 0.8x that capacity and
-                at 1.2x (overload) with p50/p99 latency (arrival to result), and
-                whether every game's credits are the same alone and in the mix;
+                [10, 1000]), TOP seeding on: one-game-at-a-time solves, the
+                batched server's closed-loop capacity under an HBM budget of a
+                quarter of the games' footprints, Poisson arrivals at 0.8x that
+                capacity and at 1.2x (overload) with p50/p99 latency (arrival to
+                result), and whether every game's credits are the same alone
+                and in each mix;
   cpu_baseline  the CPU oracle (sequential FIFO worklist, one thread) on the
                 same game: its relaxed edges per second over a bounded sample
                 of lifts (about --cpu-seconds of work), with the host's core
@@ -50,8 +52,9 @@ fields overriding the tuned ones), --no-uniform, --no-rmat-lift,
 (wall-clock cap of the legs after the timed steps: a leg that would start
 later is skipped and named in `skipped`), --max-rounds M (profiling only:
 stops each solve after M rounds; the line is then marked partial); for
-profiling, --rmat-only and --serving-only run one leg and print its JSON, and
---copy-calibration only copies 1 GiB three times (the counter scale).
+profiling, --rmat-only and --serving-only run one leg and print its JSON,
+--no-legs stops after the timed steps, and --copy-calibration only copies
+1 GiB three times (the counter scale).
 """
 from __future__ import annotations
 
@@ -276,7 +279,7 @@ def lift_sweeps(eg, game, fstar, stream, shape, sweeps):
                 f, st, rc = g.solve(max_rounds=1, resume=True, allow_timeout=True)
                 kt += st["t_round_kernels"]
                 mb += st["model_bytes"]
-            strat = strategy_timing(g, game) if not shape.get("partition") else None
+            strat = strategy_timing(g, game) if not shape.get("partition") and shape.get("hub_cache", 0) >= 0 else None
     us = kt / sweeps * 1e6
     gbps = mb / kt / 1e9
     return {"us_per_round": us, "model_bytes_per_round": mb / sweeps, "achieved": gbps,
@@ -287,11 +290,12 @@ def rmat_lift_leg(eg, game, fstar, stream, base, sweeps):
     """Full-frontier lift rounds of the R-MAT scale-22 game: every vertex is
     lifted from the least fixpoint, so nothing changes and the round is the
     lift alone (edge stream, gathers of f, reductions), against the HBM
-    roofline; unsliced (the solve's shape) and target-sliced."""
+    roofline: in place (cut tiles, with and without the LDS copy of the
+    hubs), per-XCD sliced and slice-major, in the tuned occupancy."""
     res = {"workload": "R-MAT scale 22, edge factor 16: full-frontier lift rounds from the least fixpoint (every "
                        "vertex lifted, none changes), int64 values", "n": game.n, "m": game.m}
-    for label, over in (("unsliced", {}), ("unsliced_no_hub_cache", {"hub_cache": -1}), ("sliced", {"partition": 2}),
-                        ("slice_major", {"partition": 3})):
+    for label, over in (("in_place", {"partition": 0}), ("in_place_no_hub_cache", {"partition": 0, "hub_cache": -1}),
+                        ("sliced", {"partition": 2}), ("slice_major", {"partition": 3})):
         r, strat = lift_sweeps(eg, game, fstar, stream, dict(base, **over), sweeps)
         res[label] = r
         if strat:
@@ -364,13 +368,15 @@ def main():
     ap.add_argument("--mode", default="seeded", choices=["seeded", "plain"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--serve-games", type=int, default=32)
+    ap.add_argument("--serve-games", type=int, default=128)
     ap.add_argument("--shape", default="", help="launch-shape overrides, e.g. blocks_per_cu=4")
     ap.add_argument("--no-uniform", action="store_true")
     ap.add_argument("--no-rmat-lift", action="store_true")
     ap.add_argument("--rmat-sweeps", type=int, default=10)
     ap.add_argument("--budget-s", type=float, default=420.0)
     ap.add_argument("--max-rounds", type=int, default=0)
+    ap.add_argument("--no-legs", action="store_true",
+                    help="only the timed steps and their line (profiling the headline kernels)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB on the device three times (scales the FETCH_SIZE/WRITE_SIZE counters)")
     ap.add_argument("--serving-only", action="store_true",
@@ -429,7 +435,7 @@ def main():
     t0 = time.perf_counter()
     g = ctx.create(game)
     log(f"create: {time.perf_counter() - t0:.2f} s (upload {g.create_stats['t_upload'] * 1e3:.1f} ms, "
-        f"reverse CSR {g.create_stats['t_rcsr'] * 1e3:.1f} ms)")
+        f"reverse CSR {g.create_stats['t_rcsr'] * 1e3:.1f} ms, sliced copy {g.create_stats['t_slices'] * 1e3:.1f} ms)")
     # pinned host memory for the credits (the caller's choice of buffer: the
     # device-to-host copy then runs at full PCIe rate)
     out = torch.empty(game.n, dtype=torch.int64, pin_memory=True).numpy()
@@ -506,6 +512,10 @@ def main():
     g.destroy()
     ctx.close()
 
+    if args.no_legs:
+        line["skipped"] = ["all legs (--no-legs)"]
+        print(json.dumps(line), flush=True)
+        return
     skipped = []
     t_legs = time.perf_counter()
 

@@ -107,7 +107,7 @@ typedef struct {
                                 per edge of device memory (the weights of the predecessor lists) */
   int scc_schedule;          /* 1 = the component schedule (the refinement proposed in Sec. 6): eg_solve
                                 first finds the strongly connected components of the game graph and the
-                                levels of their condensation (once per game, 13 bytes per vertex of device
+                                levels of their condensation (once per game, 21 bytes per vertex of device
                                 memory), then solves level by level from the sink components up, each
                                 level from all of its vertices, with predecessors on higher levels kept
                                 out of the active set until their level starts.  Exact (a level's
@@ -163,6 +163,7 @@ typedef struct {
   uint64_t scc_components; /* scc_schedule: strongly connected components of the game graph */
   uint64_t scc_levels;     /* scc_schedule: levels of the condensation (sink components are level 0) */
   double t_scc;            /* scc_schedule: wall time of finding them (first solve of the game only), seconds */
+  double t_slices;         /* eg_create: the edge copy grouped by target slice (partition 2 or 3), seconds */
 } eg_stats;
 
 /* What eg_check derives from a valid game. */
@@ -266,7 +267,7 @@ int eg_strategy(eg_game* g, int32_t* choice, double* t_kernel);
 /* The strongly connected components of the game graph and the levels of their
  * condensation, the order of the component schedule (the refinement proposed
  * in Sec. 6; see eg_config.scc_schedule), computed on the device at the first
- * call or schedule solve of g and kept with the game (13 bytes per vertex).
+ * call or schedule solve of g and kept with the game (21 bytes per vertex).
  * comp, level (n entries each, caller-owned host memory, caller's numbering):
  * comp[v] labels v's component (two vertices share a label exactly when each
  * reaches the other; labels are vertex ids of the device numbering, so they

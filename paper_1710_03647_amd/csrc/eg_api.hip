@@ -307,7 +307,8 @@ namespace eg {
 // round.  Measured to the fixpoint, unsliced rounds won on every large game
 // tried (uniform 2^20: 66 s against 158 s; R-MAT 2^18: 6.4 s against 21 s).
 uint32_t choose_parts(int32_t n, int64_t, int vbits, int mode) {
-  if (n > (1 << PTILE_SHIFT)) return 1;
+  // the chunk counters of the build reuse the n + 1 words of a cursor
+  if (n > (1 << PTILE_SHIFT) || (uint64_t)((n + PTILE - 1) / PTILE) * 64 > (uint64_t)n) return 1;
   if (mode == 2) return 8;  // one slice per XCD
   if (mode == 3) {
     // slice-major: slices of about SL_SLICE_BYTES of f, 8 to 64 of them
@@ -376,7 +377,7 @@ size_t staging_bytes(int32_t n, int64_t m, bool host_inputs, bool weights) {
 }
 
 hipError_t upload_game(const eg_game_desc* d, const HostPrep& prep, DevGame& dg, void* staging, hipStream_t s,
-                       hipEvent_t after_layout) {
+                       hipEvent_t after_layout, hipEvent_t after_rcsr) {
   const size_t nn = (size_t)d->n, mm = (size_t)d->m;
   const bool host_in = d->mem == EG_MEM_HOST;
   char* sb = (char*)staging;
@@ -428,6 +429,7 @@ hipError_t upload_game(const eg_game_desc* d, const HostPrep& prep, DevGame& dg,
   if ((r = launch_reverse_csr(dg.rs, dg.edges, d->n, (uint32_t)mm, (uint32_t*)dg.rev_off, (int32_t*)dg.rev_src,
                               (int32_t*)dg.rev_w, cursor, scan_tmp, scan_words, rx, s)) != hipSuccess)
     return r;
+  if (after_rcsr && (r = hipEventRecord(after_rcsr, s))) return r;
   if (dg.nparts > 1) return launch_partition(dg, d_own, cursor, scan_tmp, scan_words, s);
   return hipSuccess;
 }
@@ -650,7 +652,7 @@ int eg_create(eg_ctx* ctx, const eg_game_desc* desc, eg_game** out, eg_stats* st
   auto run = [&]() -> hipError_t {
     hipError_t r;
     if ((r = hipEventRecord(g->ev[0], s)) != hipSuccess) return r;
-    if ((r = eg::upload_game(&ud, prep, dg, staging, s, g->ev[1])) != hipSuccess) return r;
+    if ((r = eg::upload_game(&ud, prep, dg, staging, s, g->ev[1], g->ev[5])) != hipSuccess) return r;
     if ((r = hipEventRecord(g->ev[2], s)) != hipSuccess) return r;
     return hipStreamSynchronize(s);
   };
@@ -701,8 +703,10 @@ int eg_create(eg_ctx* ctx, const eg_game_desc* desc, eg_game** out, eg_stats* st
     float ms = 0;
     (void)hipEventElapsedTime(&ms, g->ev[0], g->ev[1]);
     st->t_upload = ms * 1e-3;
-    (void)hipEventElapsedTime(&ms, g->ev[1], g->ev[2]);
+    (void)hipEventElapsedTime(&ms, g->ev[1], g->ev[5]);
     st->t_rcsr = ms * 1e-3;
+    (void)hipEventElapsedTime(&ms, g->ev[5], g->ev[2]);
+    st->t_slices = ms * 1e-3;
   }
   {
     std::lock_guard<std::mutex> lock(ctx->games_mu);

@@ -121,6 +121,9 @@ struct SccBuf {
   uint8_t* mark;       // n: reached from the root in a phase
   uint32_t* flag;      // change counter of a sweep
   int32_t* max_level;  // next word: the largest level
+  int32_t* long_in;    // n: vertices with more than SCC_LONG predecessor entries (taken a block each)
+  int32_t* long_out;   // n: vertices with more than SCC_LONG out-edges
+  uint32_t* nlong;     // 2 words: the lengths of long_in and long_out
 };
 struct SccInfo {
   uint32_t components, levels;
@@ -217,7 +220,7 @@ int host_view(const eg_game_desc* desc, hipStream_t s, HostCopy& hc, eg_game_des
 // completed (weights: room for the reverse weights' build).
 size_t staging_bytes(int32_t n, int64_t m, bool host_inputs, bool weights);
 hipError_t upload_game(const eg_game_desc* d, const HostPrep& prep, DevGame& dg, void* staging, hipStream_t s,
-                       hipEvent_t after_layout);
+                       hipEvent_t after_layout, hipEvent_t after_rcsr = nullptr);
 hipError_t launch_epoch(const BatchTable& bt, int grid, hipStream_t s);
 // budget_ticks: 0, or a time budget per slot in ticks of the 100 MHz realtime counter
 hipError_t launch_batch_small(const BatchTable& bt, uint32_t max_rounds, uint64_t budget_ticks, hipStream_t s);

@@ -394,23 +394,60 @@ __device__ __forceinline__ uint32_t chunk_of(uint32_t v, uint32_t tgt, uint32_t 
   return (v / PTILE) * nparts + tgt / part_size;
 }
 
+// The copy is built like the buckets of the reverse CSR: each block takes
+// PT_CHUNK consecutive edges (whose sources lie in at most PT_TILES tiles,
+// since every vertex has an out-edge), counts its (tile, slice) chunks in LDS
+// and adds the non-zero counts to the chunk totals; after a scan of the
+// totals it counts again, reserves one range per non-empty chunk with one
+// atomic and writes its records there.  The sources come from chunk_sources.
+constexpr uint32_t PT_CHUNK = 4 * RB_SUB;              // edges per block
+constexpr uint32_t PT_TILES = PT_CHUNK / PTILE + 2;    // tiles a block's edges can touch
+constexpr uint32_t PT_KEYS = PT_TILES * 64;            // (tile, slice) counters, at most 64 slices
+
 template <bool SCATTER>
-__global__ void k_part_edges(const uint32_t* rs, const int2* edges, int32_t n, uint32_t m, uint32_t chunk,
-                             uint32_t nparts, uint32_t part_size, uint32_t* cnt, int2* pedges) {
-  const uint64_t first = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * chunk;
-  if (first >= m) return;
-  const uint32_t last = (uint32_t)std::min<uint64_t>(m, first + chunk);
-  int32_t v = source_of(rs, n, (uint32_t)first);
-  for (uint32_t e = (uint32_t)first; e < last; e++) {
-    while ((rs[v + 1] & ROW_MASK) <= e) v++;
-    const int2 ed = edges[e];
-    const uint32_t c = chunk_of((uint32_t)v, (uint32_t)ed.x, nparts, part_size);
-    if (SCATTER) {
-      const uint32_t slot = atomicAdd(&cnt[c], 1u);
-      pedges[slot] = make_int2((int32_t)((uint32_t)ed.x | (((uint32_t)v % PTILE) << PTILE_SHIFT)), ed.y);
-    } else {
-      atomicAdd(&cnt[c], 1u);
+__global__ __launch_bounds__(BLOCK) void k_part_edges(const uint32_t* rs, const int2* edges, int32_t n, uint32_t m,
+                                                      uint32_t nparts, uint32_t part_size, uint32_t* cnt,
+                                                      int2* pedges) {
+  __shared__ uint32_t lcnt[PT_KEYS];  // counts, then the first slot of the block's range per chunk
+  __shared__ uint32_t lcur[SCATTER ? PT_KEYS : 1];
+  __shared__ uint32_t srcl[RB_SUB];
+  __shared__ uint32_t wmax[BLOCK / WAVE];
+  __shared__ uint32_t s_va, s_more[2], s_t0;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t e0 = blockIdx.x * PT_CHUNK, e1 = min(m, e0 + PT_CHUNK);
+  for (uint32_t i = tid; i < PT_KEYS; i += BLOCK) {
+    lcnt[i] = 0;
+    if (SCATTER) lcur[i] = 0;
+  }
+  // the tile of the block's first edge (every later edge is in it or after it)
+  if (tid == 0) s_t0 = (uint32_t)source_of(rs, n, e0) / PTILE;
+  block_sync();
+  const uint32_t t0 = s_t0;
+  for (int pass = 0; pass < (SCATTER ? 2 : 1); pass++) {
+    for (uint32_t sub = e0; sub < e1; sub += RB_SUB) {
+      const uint32_t len = min(e1 - sub, RB_SUB);
+      chunk_sources(rs, n, sub, len, srcl, wmax, &s_va, s_more);
+      for (uint32_t x = tid; x < len; x += BLOCK) {
+        const int2 ed = edges[sub + x];
+        const uint32_t src = srcl[x];
+        const uint32_t key = (src / PTILE - t0) * nparts + (uint32_t)ed.x / part_size;
+        if (pass == 0) {
+          atomicAdd(&lcnt[key], 1u);
+        } else {
+          const uint32_t slot = lcnt[key] + atomicAdd(&lcur[key], 1u);
+          pedges[slot] = make_int2((int32_t)((uint32_t)ed.x | ((src % PTILE) << PTILE_SHIFT)), ed.y);
+        }
+      }
+      block_sync();  // srcl is rewritten by the next step
     }
+    const uint32_t nkeys = PT_TILES * nparts;
+    for (uint32_t k = tid; k < nkeys; k += BLOCK) {
+      if (!lcnt[k]) continue;
+      const uint32_t c = (t0 + k / nparts) * nparts + k % nparts;
+      if (!SCATTER) atomicAdd(&cnt[c], lcnt[k]);
+      else if (pass == 0) lcnt[k] = atomicAdd(&cnt[c], lcnt[k]);
+    }
+    block_sync();
   }
 }
 
@@ -434,16 +471,16 @@ hipError_t launch_partition(const DevGame& dg, const uint8_t*, uint32_t* cursor,
   if (nchunks > (uint32_t)dg.n || scan_words < scan_tmp_words((size_t)nchunks + 1)) return hipErrorInvalidValue;
   hipError_t e = hipMemsetAsync(cursor, 0, 4 * ((size_t)nchunks + 1), s);
   if (e != hipSuccess) return e;
-  const uint32_t chunk = 16;
-  const int grid_s = (int)std::max<uint64_t>(1, ((uint64_t)dg.m + (uint64_t)chunk * BLOCK - 1) / ((uint64_t)chunk * BLOCK));
-  hipLaunchKernelGGL(k_part_edges<false>, dim3(grid_s), dim3(BLOCK), 0, s, dg.rs, dg.edges, dg.n, dg.m, chunk,
-                     dg.nparts, dg.part_size, cursor, (int2*)nullptr);
+  if (dg.nparts > 64) return hipErrorInvalidValue;
+  const int grid_s = (int)std::max<uint64_t>(1, ((uint64_t)dg.m + PT_CHUNK - 1) / PT_CHUNK);
+  hipLaunchKernelGGL(k_part_edges<false>, dim3(grid_s), dim3(BLOCK), 0, s, dg.rs, dg.edges, dg.n, dg.m, dg.nparts,
+                     dg.part_size, cursor, (int2*)nullptr);
   e = exclusive_scan(cursor, (uint32_t*)dg.poff, (size_t)nchunks + 1, scan_tmp, s);
   if (e != hipSuccess) return e;
   e = hipMemcpyAsync(cursor, dg.poff, 4 * (size_t)nchunks, hipMemcpyDeviceToDevice, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_part_edges<true>, dim3(grid_s), dim3(BLOCK), 0, s, dg.rs, dg.edges, dg.n, dg.m, chunk,
-                     dg.nparts, dg.part_size, cursor, (int2*)dg.pedges);
+  hipLaunchKernelGGL(k_part_edges<true>, dim3(grid_s), dim3(BLOCK), 0, s, dg.rs, dg.edges, dg.n, dg.m, dg.nparts,
+                     dg.part_size, cursor, (int2*)dg.pedges);
   const int grid_w = (int)std::max<int64_t>(1, std::min<int64_t>((((int64_t)dg.n + 31) / 32 + BLOCK - 1) / BLOCK, 4096));
   hipLaunchKernelGGL(k_owner_words, dim3(grid_w), dim3(BLOCK), 0, s, dg.rs, dg.n, (uint32_t*)dg.own_bits);
   return hipGetLastError();

@@ -24,8 +24,9 @@
 // Each phase assigns at least the component of the largest unassigned id.
 // Component labels are vertex ids: the root (or the trimmed vertex) itself.
 //
-// Rows of up to SCC_SHORT entries are scanned by their vertex's lane; longer
-// ones by the whole wave, so that hubs cost deg / 64 steps.
+// Rows of up to SCC_SHORT entries are scanned by their vertex's lane, longer
+// ones by the whole wave, and in the colouring and level sweeps rows above
+// SCC_LONG by a whole block.
 #include "eg_internal.h"
 
 namespace eg {
@@ -34,6 +35,11 @@ namespace {
 constexpr int WAVE = 64;
 constexpr int BLOCK = 256;
 constexpr uint32_t SCC_SHORT = 32;
+// Rows longer than this are listed once and folded by a whole block each in
+// the colouring and level sweeps: the hubs of power-law games sit next to
+// each other after renumbering, and one wave would take them in turn.
+constexpr uint32_t SCC_LONG = 2048;
+constexpr int SCC_LONG_GRID = 1024;
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
@@ -153,7 +159,7 @@ __global__ __launch_bounds__(BLOCK) void k_scc_color(DevGame g, SccBuf sc) {
         const int32_t x = val(k);
         best = x > best ? x : best;
       }
-    unsigned long long longs = __ballot(live && pe - pb > SCC_SHORT);
+    unsigned long long longs = __ballot(live && pe - pb > SCC_SHORT && pe - pb <= SCC_LONG);
     while (longs) {
       const uint32_t src = (uint32_t)__ffsll((long long)longs) - 1;
       longs &= longs - 1;
@@ -206,6 +212,98 @@ __global__ __launch_bounds__(BLOCK) void k_scc_mark(DevGame g, SccBuf sc) {
     }
   }
   if (hits) atomicAdd(sc.flag, hits);
+}
+
+// Block-wide max of one value per thread (every thread gets it).
+__device__ __forceinline__ int32_t block_max(int32_t x, int32_t* wred) {
+  const uint32_t lane = lane_id(), wid = threadIdx.x / WAVE;
+#pragma unroll
+  for (int o = 1; o < WAVE; o <<= 1) {
+    const int32_t y = __shfl_xor(x, o, WAVE);
+    x = y > x ? y : x;
+  }
+  if (lane == 0) wred[wid] = x;
+  block_sync();
+  int32_t m = wred[0];
+  for (uint32_t w = 1; w < BLOCK / WAVE; w++) m = wred[w] > m ? wred[w] : m;
+  block_sync();  // wred may be rewritten by the next call
+  return m;
+}
+
+// the vertices whose rows the block kernels below take (once per game)
+__global__ __launch_bounds__(BLOCK) void k_scc_long_lists(DevGame g, SccBuf sc) {
+  const uint32_t n = (uint32_t)g.n;
+  for (uint32_t v0 = blockIdx.x * blockDim.x + threadIdx.x - lane_id(); v0 < n; v0 += gridDim.x * blockDim.x) {
+    const uint32_t v = v0 + lane_id();
+    const bool in = v < n;
+    const bool li = in && g.rev_off[v + 1] - g.rev_off[v] > SCC_LONG;
+    const bool lo = in && out_end(g, v) - out_begin(g, v) > SCC_LONG;
+    unsigned long long m = __ballot(li);
+    if (m) {
+      const uint32_t leader = __ffsll((long long)m) - 1;
+      uint32_t base = 0;
+      if (lane_id() == leader) base = atomicAdd(&sc.nlong[0], (uint32_t)__popcll(m));
+      base = __shfl(base, (int)leader, WAVE);
+      if (li) sc.long_in[base + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))] = (int32_t)v;
+    }
+    m = __ballot(lo);
+    if (m) {
+      const uint32_t leader = __ffsll((long long)m) - 1;
+      uint32_t base = 0;
+      if (lane_id() == leader) base = atomicAdd(&sc.nlong[1], (uint32_t)__popcll(m));
+      base = __shfl(base, (int)leader, WAVE);
+      if (lo) sc.long_out[base + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))] = (int32_t)v;
+    }
+  }
+}
+
+// colour of the long predecessor lists: one block per listed vertex
+__global__ __launch_bounds__(BLOCK) void k_scc_color_long(DevGame g, SccBuf sc) {
+  __shared__ int32_t wred[BLOCK / WAVE];
+  const uint32_t cnt = sc.nlong[0];
+  uint32_t hits = 0;
+  for (uint32_t i = blockIdx.x; i < cnt; i += gridDim.x) {
+    const int32_t v = sc.long_in[i];
+    if (sc.comp[v] >= 0) continue;  // block-uniform
+    int32_t best = -1;
+    for (uint32_t k = g.rev_off[v] + threadIdx.x; k < g.rev_off[v + 1]; k += BLOCK) {
+      const int32_t p = g.rev_src[k];
+      const int32_t x = sc.comp[p] < 0 ? sc.color[p] : -1;
+      best = x > best ? x : best;
+    }
+    best = block_max(best, wred);
+    if (threadIdx.x == 0 && best > sc.color[v]) {
+      sc.color[v] = best;
+      hits++;
+    }
+  }
+  if (hits) atomicAdd(sc.flag, hits);
+}
+
+// level of the long out-rows: one block per listed vertex
+__global__ __launch_bounds__(BLOCK) void k_scc_level_long(DevGame g, SccBuf sc) {
+  __shared__ int32_t wred[BLOCK / WAVE];
+  const uint32_t cnt = sc.nlong[1];
+  uint32_t hits = 0;
+  int32_t top = 0;
+  for (uint32_t i = blockIdx.x; i < cnt; i += gridDim.x) {
+    const int32_t v = sc.long_out[i];
+    const int32_t cv = sc.comp[v];
+    int32_t best = 0;
+    for (uint32_t k = out_begin(g, v) + threadIdx.x; k < out_end(g, v); k += BLOCK) {
+      const int32_t u = g.edges[k].x;
+      const int32_t x = sc.lev[u] + (sc.comp[u] != cv ? 1 : 0);
+      best = x > best ? x : best;
+    }
+    best = block_max(best, wred);
+    if (threadIdx.x == 0 && best > sc.lev[v]) {
+      sc.lev[v] = best;
+      hits++;
+    }
+    top = best > top ? best : top;
+  }
+  if (hits) atomicAdd(sc.flag, hits);
+  if (threadIdx.x == 0 && top) atomicMax(sc.max_level, top);
 }
 
 // start of a colour phase: every unassigned vertex takes its own id
@@ -264,7 +362,7 @@ __global__ __launch_bounds__(BLOCK) void k_scc_level(DevGame g, SccBuf sc) {
         const int32_t x = val(k, cv);
         best = x > best ? x : best;
       }
-    unsigned long long longs = __ballot(in && oe - ob > SCC_SHORT);
+    unsigned long long longs = __ballot(in && oe - ob > SCC_SHORT && oe - ob <= SCC_LONG);
     while (longs) {
       const uint32_t src = (uint32_t)__ffsll((long long)longs) - 1;
       longs &= longs - 1;
@@ -356,7 +454,7 @@ hipError_t until_stable(const SccBuf& sc, uint32_t* h_flag, hipStream_t s, F lau
 size_t scc_bytes(int32_t n) {
   const size_t nn = (size_t)n;
   auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
-  return 3 * up(4 * nn) + up(nn) + up(8);
+  return 5 * up(4 * nn) + up(nn) + up(16);
 }
 
 void bind_scc(SccBuf& sc, void* base, int32_t n) {
@@ -373,6 +471,11 @@ void bind_scc(SccBuf& sc, void* base, int32_t n) {
   b += up(nn);
   sc.flag = (uint32_t*)b;
   sc.max_level = (int32_t*)(b + 4);
+  sc.nlong = (uint32_t*)(b + 8);
+  b += up(16);
+  sc.long_in = (int32_t*)b;
+  b += up(4 * nn);
+  sc.long_out = (int32_t*)b;
 }
 
 hipError_t compute_scc(const DevGame& g, const SccBuf& sc, uint32_t* h_word, hipStream_t s, SccInfo* info) {
@@ -382,6 +485,8 @@ hipError_t compute_scc(const DevGame& g, const SccBuf& sc, uint32_t* h_word, hip
   uint64_t sweeps = 0, phases = 0;
   const uint64_t cap = 2 * (uint64_t)n + 64;
   hipLaunchKernelGGL(k_scc_reset, dim3(grid), dim3(BLOCK), 0, s, n, sc);
+  if ((e = hipMemsetAsync(sc.nlong, 0, 8, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_scc_long_lists, dim3(grid), dim3(BLOCK), 0, s, g, sc);
   for (;;) {
     if (phases > (uint64_t)n) return hipErrorUnknown;  // each phase assigns a component
     e = until_stable(sc, h_word, s, [&] { hipLaunchKernelGGL(k_scc_trim, dim3(grid), dim3(BLOCK), 0, s, g, sc); },
@@ -395,7 +500,11 @@ hipError_t compute_scc(const DevGame& g, const SccBuf& sc, uint32_t* h_word, hip
     if (*h_word == 0) break;
     phases++;
     hipLaunchKernelGGL(k_scc_color_init, dim3(grid), dim3(BLOCK), 0, s, n, sc);
-    e = until_stable(sc, h_word, s, [&] { hipLaunchKernelGGL(k_scc_color, dim3(grid), dim3(BLOCK), 0, s, g, sc); },
+    e = until_stable(sc, h_word, s,
+                     [&] {
+                       hipLaunchKernelGGL(k_scc_color, dim3(grid), dim3(BLOCK), 0, s, g, sc);
+                       hipLaunchKernelGGL(k_scc_color_long, dim3(SCC_LONG_GRID), dim3(BLOCK), 0, s, g, sc);
+                     },
                      &sweeps, cap);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_scc_roots, dim3(grid), dim3(BLOCK), 0, s, n, sc);
@@ -406,7 +515,11 @@ hipError_t compute_scc(const DevGame& g, const SccBuf& sc, uint32_t* h_word, hip
     hipLaunchKernelGGL(k_scc_assign, dim3(grid), dim3(BLOCK), 0, s, n, sc);
   }
   if ((e = hipMemsetAsync(sc.max_level, 0, 4, s)) != hipSuccess) return e;
-  e = until_stable(sc, h_word, s, [&] { hipLaunchKernelGGL(k_scc_level, dim3(grid), dim3(BLOCK), 0, s, g, sc); },
+  e = until_stable(sc, h_word, s,
+                   [&] {
+                     hipLaunchKernelGGL(k_scc_level, dim3(grid), dim3(BLOCK), 0, s, g, sc);
+                     hipLaunchKernelGGL(k_scc_level_long, dim3(SCC_LONG_GRID), dim3(BLOCK), 0, s, g, sc);
+                   },
                    &sweeps, cap);
   if (e != hipSuccess) return e;
   if ((e = hipMemsetAsync(sc.flag, 0, 4, s)) != hipSuccess) return e;

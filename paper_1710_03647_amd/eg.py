@@ -67,7 +67,7 @@ class eg_stats(ctypes.Structure):
                 ("dense_rounds", ctypes.c_uint64), ("seeded", ctypes.c_uint64), ("seed_passes", ctypes.c_uint64),
                 ("all_rounds", ctypes.c_uint64), ("t_seed", ctypes.c_double),
                 ("filtered_preds", ctypes.c_uint64), ("scc_components", ctypes.c_uint64),
-                ("scc_levels", ctypes.c_uint64), ("t_scc", ctypes.c_double)]
+                ("scc_levels", ctypes.c_uint64), ("t_scc", ctypes.c_double), ("t_slices", ctypes.c_double)]
 
     def to_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
