@@ -30,11 +30,12 @@ Also reported (each leg once, after the timed steps, each under a time cap):
   uniform       the uniform random game (n = 2^20, out-degree 16, weights in
                 [-1000, 1000], seed 2): one plain solve to the fixpoint (no
                 seeding) and one seeded solve, credits compared;
-  serving       the first --serve-games (128) games of the serving stream (n
+  serving       the first --serve-games (32) games of the serving stream (n
                 log-uniform in [1e3, 1e5], out-degree U{2..16}, W log-uniform in
                 [10, 1000]), TOP seeding on: one-game-at-a-time solves, the
                 batched server's closed-loop capacity under an HBM budget of a
-                quarter of the games' footprints, Poisson arrivals at 0.8x that
+                quarter of the games' footprints (all games, and the typical
+                ones that solve alone within 0.5 s), Poisson arrivals at 0.8x that
                 capacity and at 1.2x (overload) with p50/p99 latency (arrival to
                 result), and whether every game's credits are the same alone
                 and in each mix;
@@ -185,12 +186,30 @@ def poisson_run(ctx, synth, games, rate):
     return lat, time.perf_counter() - t0, outs
 
 
+def closed_loop(eg, ctx, games, alone):
+    """Every game submitted at once, every result awaited: wall time, games
+    that waited for admission, whether each result equals the game's alone."""
+    import numpy as np
+
+    t0 = time.perf_counter()
+    tickets = [ctx.submit(g) for g in games]
+    queued, same = 0, True
+    for g, t, a in zip(games, tickets, alone):
+        rc, f, st = ctx.wait(t, g.n)
+        same &= bool(np.array_equal(f, a))
+        queued += st["t_queue"] > 1e-3
+    return time.perf_counter() - t0, queued, same
+
+
 def serving_report(eg, synth, count):
     """One-at-a-time vs batched serving on the first `count` stream games, both
     with TOP seeding; the HBM budget of the server is a quarter of the games'
-    summed footprints (at least the largest one), so admission waits for
-    memory; Poisson arrivals at 0.8x the batched closed-loop capacity, and an
-    overload run at 1.2x; every game's credits compared alone and in each mix."""
+    summed footprints (at least three times the largest one), so admission
+    waits for memory.  Closed loop on all of them and on the typical ones
+    (those that solve alone within 0.5 s: a slow trap's time is its own serial
+    rounds, whatever it shares the device with); Poisson arrivals at 0.8x the
+    closed-loop capacity, and an overload run at 1.2x; every game's credits
+    compared alone and in each mix."""
     import numpy as np
 
     from paper_1710_03647_amd import tune
@@ -201,43 +220,52 @@ def serving_report(eg, synth, count):
     serve_shape = tune.serving_config()
     # the server's footprint of a game also holds its upload and seeding scratch
     budget_bytes = max(need // 4, 3 * max(feet))
-    alone = []
+    alone, t_alone = [], []
     with eg.Context(0, top_seeding=1) as ctx:
-        t0 = time.perf_counter()
-        for g in games:
+        for i, g in enumerate(games):
+            t0 = time.perf_counter()
             with ctx.create(g) as h:
                 alone.append(h.solve()[0].copy())
-        t_one = time.perf_counter() - t0
-    log(f"serving: one at a time {count / t_one:.2f} games/s ({t_one:.1f} s)")
+            t_alone.append(time.perf_counter() - t0)
+            if i % 8 == 7:
+                log(f"serving: {i + 1} of {count} games solved one at a time ({sum(t_alone):.1f} s)")
+    t_one = sum(t_alone)
+    typical = [i for i, t in enumerate(t_alone) if t <= 0.5]
+    t_one_typ = sum(t_alone[i] for i in typical)
+    log(f"serving: one at a time {count / t_one:.2f} games/s ({t_one:.1f} s); {len(typical)} typical games "
+        f"{len(typical) / t_one_typ:.2f} games/s")
     res = {"games": count, "workload": f"first {count} games of the serving stream (seed 5)",
            "mode": "TOP seeding on, one at a time (eg_solve) and served (eg_submit)",
            "hbm_budget_bytes": budget_bytes, "footprint_sum_bytes": need, "server_shape": serve_shape,
-           "one_at_a_time_games_per_s": count / t_one}
-    same = True
+           "one_at_a_time_games_per_s": count / t_one,
+           "slow_games": {i: round(t, 2) for i, t in enumerate(t_alone) if t > 0.5}}
     with eg.Context(0, hbm_budget_bytes=budget_bytes, top_seeding=1, **serve_shape) as ctx:
-        t0 = time.perf_counter()
-        tickets = [ctx.submit(g) for g in games]
-        queued = 0
-        for i, (g, t) in enumerate(zip(games, tickets)):
-            rc, f, st = ctx.wait(t, g.n)
-            same &= bool(np.array_equal(f, alone[i]))
-            queued += st["t_queue"] > 1e-3
-        t_cap = time.perf_counter() - t0
-        res["closed_loop_games_waiting_for_admission"] = queued
+        t_cap, queued, same = closed_loop(eg, ctx, games, alone)
         cap = count / t_cap
-        log(f"serving: batched closed loop {cap:.2f} games/s ({t_cap:.1f} s)")
+        log(f"serving: batched closed loop {cap:.2f} games/s ({t_cap:.1f} s), {queued} waited for admission")
+        tg = [games[i] for i in typical]
+        t_typ, queued_typ, same_typ = closed_loop(eg, ctx, tg, [alone[i] for i in typical])
+        same &= same_typ
+        log(f"serving: typical games batched {len(tg) / t_typ:.2f} games/s against {len(tg) / t_one_typ:.2f} "
+            f"one at a time")
         rate = 0.8 * cap
         lat, t_poi, outs = poisson_run(ctx, synth, games, rate)
         same &= all(np.array_equal(f, a) for f, a in zip(outs, alone))
+        log(f"serving: Poisson run done ({t_poi:.1f} s)")
         lat_o, t_over, outs = poisson_run(ctx, synth, games, 1.2 * cap)
         same &= all(np.array_equal(f, a) for f, a in zip(outs, alone))
-    res.update({"batched_capacity_games_per_s": cap, "poisson_rate_per_s": rate,
-                "poisson_games_per_s": count / t_poi,
+    res.update({"batched_capacity_games_per_s": cap, "closed_loop_games_waiting_for_admission": queued,
+                "batched_vs_one_at_a_time": cap / (count / t_one),
+                "typical_games": len(tg),
+                "typical_one_at_a_time_games_per_s": len(tg) / t_one_typ,
+                "typical_batched_games_per_s": len(tg) / t_typ,
+                "typical_batched_vs_one_at_a_time": (len(tg) / t_typ) / (len(tg) / t_one_typ),
+                "typical_games_waiting_for_admission": queued_typ,
+                "poisson_rate_per_s": rate, "poisson_games_per_s": count / t_poi,
                 "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
                 "overload_rate_per_s": 1.2 * cap, "overload_games_per_s": count / t_over,
                 "overload_p50_latency_s": float(np.percentile(lat_o, 50)),
                 "overload_p99_latency_s": float(np.percentile(lat_o, 99)),
-                "batched_vs_one_at_a_time": cap / (count / t_one),
                 "alone_equals_mix": same})
     log(f"serving: Poisson {rate:.2f}/s -> p50 {res['p50_latency_s']:.3f} s, p99 {res['p99_latency_s']:.3f} s; "
         f"overload {1.2 * cap:.2f}/s -> p50 {res['overload_p50_latency_s']:.3f} s, "
@@ -368,7 +396,7 @@ def main():
     ap.add_argument("--mode", default="seeded", choices=["seeded", "plain"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--serve-games", type=int, default=128)
+    ap.add_argument("--serve-games", type=int, default=32)
     ap.add_argument("--shape", default="", help="launch-shape overrides, e.g. blocks_per_cu=4")
     ap.add_argument("--no-uniform", action="store_true")
     ap.add_argument("--no-rmat-lift", action="store_true")
