@@ -802,7 +802,7 @@ static int solve_impl(eg_game* g, const eg_solve_opts* opts, int64_t* credits, e
   // representation of the active set: a flag sweep for large sets, a list
   // for medium ones, and for small ones a single block running many rounds
   // ALL: every vertex lifted, nothing activated (while the frontier covers
-  // about every vertex; unsliced games only)
+  // about every vertex; not with per-XCD slices)
   enum { SPARSE, DENSE, SMALL, ALL };
   auto pick = [&](uint64_t size) { return size <= small_limit ? SMALL : size >= dense_at ? DENSE : SPARSE; };
   int mode = pick(active);
