@@ -806,7 +806,14 @@ static int solve_impl(eg_game* g, const eg_solve_opts* opts, int64_t* credits, e
   enum { SPARSE, DENSE, SMALL, ALL };
   auto pick = [&](uint64_t size) { return size <= small_limit ? SMALL : size >= dense_at ? DENSE : SPARSE; };
   int mode = pick(active);
-  if (active && mode != DENSE) HIPCHK(eg::launch_compact(dg, 1, grid, s));
+  // Each initially active vertex rises in round 1 (its flag means that its
+  // lift from 0 is positive).  When their predecessors would cover V, the
+  // first rounds lift every vertex instead of flagging predecessors one
+  // store at a time.
+  if (mode == DENSE && !o.resume && !scc && (dg.nparts == 1 || dg.slice_major) &&
+      (double)active * g->avg_indeg >= (double)g->n)
+    mode = ALL;
+  if (active && mode != DENSE && mode != ALL) HIPCHK(eg::launch_compact(dg, 1, grid, s));
   wide = 2 * active >= (uint64_t)g->n;
   uint32_t batch = 2;
   double t_kernels = 0;  // device time of the round kernels (back to back within a batch)
