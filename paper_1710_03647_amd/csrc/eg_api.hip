@@ -844,7 +844,7 @@ static int solve_impl(eg_game* g, const eg_solve_opts* opts, int64_t* credits, e
     }
     if (seeding && launched >= next_seed) {
       HIPCHK(hipEventRecord(g->ev[3], s));
-      HIPCHK(eg::launch_seed(dg, g->vbits, g->sb, r, s));
+      HIPCHK(eg::launch_seed(dg, g->vbits, g->sb, r, seed_passes == 0 && !o.resume, s));
       HIPCHK(hipEventRecord(g->ev[4], s));
       HIPCHK(hipMemcpyAsync(g->h_seed, g->sb.count, 4, hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
@@ -1020,9 +1020,9 @@ int eg_solve(eg_game* g, int64_t* credits, eg_stats* st) { return eg_solve_ex(g,
 namespace {
 constexpr size_t pad256(size_t x) { return (x + 255) & ~(size_t)255; }
 // the layout of eg::seed_bytes for EG_NOALLOC_MAX_N vertices
-constexpr size_t NOALLOC_SCRATCH_BYTES = 6 * pad256(4 * (size_t)EG_NOALLOC_MAX_N) +
-                                         2 * pad256((size_t)EG_NOALLOC_MAX_N) + pad256(8 * (size_t)EG_NOALLOC_MAX_N) +
-                                         pad256(4);
+constexpr size_t NOALLOC_SCRATCH_BYTES = 2 * pad256(4 * (size_t)EG_NOALLOC_MAX_N) +
+                                         3 * pad256(8 * (size_t)EG_NOALLOC_MAX_N) +
+                                         2 * pad256((size_t)EG_NOALLOC_MAX_N) + pad256(16);
 __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
 constexpr int NOALLOC_DEVICES = 64;
 std::mutex scratch_table_mu;

@@ -106,12 +106,13 @@ constexpr uint32_t HUB_BYTES = 16u << 10;       // default LDS copy of the most 
 struct SeedBuf {
   int32_t* succ;      // chosen successor in the forced subgraph, -1 if none
   int32_t* wgt;       // weight of that edge
-  int32_t* p[2];      // pointer-doubling successors (double buffered)
-  int32_t* lo[2];     // smallest vertex id on the walk so far (double buffered)
+  int2* pl[2];        // pointer doubling (double buffered): {successor 2^k steps on, smallest vertex id
+                      // on the walk so far}
   uint8_t* forced;    // 1 for player-1 vertices and for player-0 vertices of out-degree 1
   uint8_t* oncyc;     // 1 for vertices on a cycle of the chosen edges
   long long* sum;     // per cycle (indexed by its smallest vertex): total weight
-  uint32_t* count;    // 1 word: vertices newly set to TOP
+  uint32_t* count;    // 4 words: [0] vertices newly set to TOP, [1] long rows, [2] long predecessor
+                      // lists, [3] medium rows
 };
 // Strongly connected components and condensation levels (component schedule).
 struct SccBuf {
@@ -140,7 +141,9 @@ hipError_t launch_level_activate(const DevGame& g, const int32_t* lev, int32_t l
                                  hipStream_t s);
 size_t seed_bytes(int32_t n);
 void bind_seed(SeedBuf& sb, void* base, int32_t n);
-hipError_t launch_seed(const DevGame& g, int vbits, const SeedBuf& sb, uint32_t r, hipStream_t s);
+// f_zero: f is 0 everywhere (the pass before the first round of a solve that
+// does not resume), so the choice reads no values.
+hipError_t launch_seed(const DevGame& g, int vbits, const SeedBuf& sb, uint32_t r, bool f_zero, hipStream_t s);
 
 // Slot states of the batched iteration, and where a running slot's rounds run:
 // in the epochs (flag sweeps, one round per epoch) or in k_batch_small (lists,

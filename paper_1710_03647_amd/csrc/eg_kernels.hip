@@ -1679,16 +1679,20 @@ __global__ void k_seed_forced(DevGame g, SeedBuf sb) {
   }
 }
 
-// Rows of player-1 vertices up to this length are scanned by their own lane;
-// longer ones by the whole wave, SEED_UNROLL * 64 edges per step, so that a hub
-// costs deg / 256 dependent steps instead of deg.
-constexpr uint32_t SEED_SHORT = 32;
+// Edges per lane per step of the seeding scans.
 constexpr int SEED_UNROLL = 4;
-// Rows (and predecessor lists) longer than this go to a list and are scanned
-// by a whole block each in a second kernel: the hubs of power-law games sit
-// next to each other after renumbering, and one wave would take them in turn.
+// Predecessor lists of new TOP vertices up to this length are flagged by their
+// own lane, longer ones by the whole wave.
+constexpr uint32_t SEED_SHORT = 32;
+// Player-1 rows up to SEED_FLAT edges are scanned flattened per tile; longer
+// ones go to lists scanned a row per wave (up to SEED_LONG edges) and a row
+// per block, so that no tile of hubs (the hubs of power-law games sit next to
+// each other, and renumbering puts them together) holds up one block.
+// Predecessor lists longer than SEED_LONG are flagged by a block each too.
+constexpr uint32_t SEED_FLAT = 64;
 constexpr uint32_t SEED_LONG = 2048;
 constexpr int SEED_LONG_GRID = 1024;
+constexpr int SEED_MID_GRID = 2048;
 
 // Candidate order of sigma1: a negative self-loop first (player 1 can stay on
 // it forever, so it is always a certificate), then the largest term, then the
@@ -1700,18 +1704,50 @@ __device__ __forceinline__ bool seed_better(bool lb, V tb, uint32_t kb, bool la,
   return kb < ka;
 }
 
-// sigma1 for every player-1 vertex over its out-edges into the forced subgraph;
-// the single edge of every player-0 vertex of out-degree 1.
-template <typename V>
-__global__ __launch_bounds__(BLOCK) void k_seed_choose(DevGame g, SeedBuf sb, int32_t* longs_out) {
-  const V* f = (const V*)g.f;
-  const uint32_t n = (uint32_t)g.n;
+// Segmented fold over the lanes of a wave whose slots run in contiguous
+// groups: afterwards the first lane of each group holds the group's best
+// (has, x) under better(); lanes with has = false hold no candidate.
+template <typename T, typename Better>
+__device__ __forceinline__ void wave_seg_fold(bool& has, T& x, uint32_t slot, Better better) {
   const uint32_t lane = lane_id();
-  const uint32_t stride = gridDim.x * blockDim.x;
+#pragma unroll
+  for (int o = 1; o < WAVE; o <<= 1) {
+    const T xo = __shfl_down(x, o, WAVE);
+    const bool ho = __shfl_down((int)has, o, WAVE) != 0;
+    const uint32_t so = __shfl_down(slot, o, WAVE);
+    if (lane + o < (uint32_t)WAVE && so == slot && ho && (!has || better(xo, x))) {
+      x = xo;
+      has = true;
+    }
+  }
+}
+
+// sigma1 for every player-1 vertex over its out-edges into the forced
+// subgraph, and the single edge of every player-0 vertex of out-degree 1.
+// The player-1 rows of up to SEED_FLAT edges of a tile of BLOCK vertices are
+// flattened as in the lift, so that consecutive lanes read consecutive edges
+// whatever the degrees.  A candidate's rank is one 64-bit key, the negative
+// self-loop flag above the term (terms stay below 2^63), larger first, and
+// then the lower edge index.  Per chunk of the flattened range: the keys are
+// folded into the row's LDS maximum; the lanes holding that maximum fold
+// their indices into the row's LDS minimum; and the row's own thread keeps
+// the chunk's index only when the chunk raised the maximum or the row had no
+// candidate yet (an earlier chunk holds the lower indices of an equal key).
+template <typename V>
+__global__ __launch_bounds__(BLOCK) void k_seed_choose(DevGame g, SeedBuf sb, int32_t* longs_out,
+                                                       int32_t* mids_out, bool f_zero) {
   constexpr uint32_t NONE = 0xFFFFFFFFu;
-  // v0 is the wave's first vertex: the same in every lane, so ballots see the whole wave
-  for (uint32_t v0 = blockIdx.x * blockDim.x + threadIdx.x - lane; v0 < n; v0 += stride) {
-    const uint32_t v = v0 + lane;
+  constexpr int J = SEED_UNROLL;
+  __shared__ uint32_t epre[BLOCK + 1];
+  __shared__ uint32_t ebeg[BLOCK];
+  __shared__ unsigned long long kmax[BLOCK];
+  __shared__ uint32_t kidx[BLOCK];
+  __shared__ uint32_t wsum[BLOCK / WAVE];
+  const V* f = (const V*)g.f;
+  const uint32_t n = (uint32_t)g.n, tid = threadIdx.x, lane = lane_id();
+  const uint32_t ntiles = (n + BLOCK - 1) / BLOCK;
+  for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const uint32_t v = t * BLOCK + tid;
     uint32_t e0 = 0, deg = 0;
     bool p1 = false;
     if (v < n) {
@@ -1720,67 +1756,138 @@ __global__ __launch_bounds__(BLOCK) void k_seed_choose(DevGame g, SeedBuf sb, in
       deg = (g.rs[v + 1] & ROW_MASK) - e0;
       p1 = (a & OWNER_BIT) != 0;
     }
-    uint32_t kbest = NONE;
-    if (v < n && p1 && deg <= SEED_SHORT) {
-      bool lbest = false;
-      V tbest = -1;
-      for (uint32_t k0 = 0; k0 < deg; k0 += SEED_UNROLL) {
-        int2 ed[SEED_UNROLL];
-#pragma unroll
-        for (int j = 0; j < SEED_UNROLL; j++) ed[j] = g.edges[e0 + min(k0 + j, deg - 1)];
-        uint8_t fz[SEED_UNROLL];
-        V fu[SEED_UNROLL];
-#pragma unroll
-        for (int j = 0; j < SEED_UNROLL; j++) {
-          fz[j] = sb.forced[ed[j].x];
-          fu[j] = f[ed[j].x];
-        }
-#pragma unroll
-        for (int j = 0; j < SEED_UNROLL; j++) {
-          const uint32_t k = k0 + j;
-          if (k >= deg || !fz[j]) continue;
-          const bool l = ed[j].x == (int32_t)v && ed[j].y < 0;
-          V tm = fu[j] - (V)ed[j].y;
-          tm = tm > V(0) ? tm : V(0);
-          if (kbest == NONE || seed_better<V>(l, tm, k, lbest, tbest, kbest)) {
-            lbest = l;
-            tbest = tm;
-            kbest = k;
-          }
-        }
-      }
-    } else if (v < n && !p1 && deg == 1) {
-      kbest = 0;
-    }
-    // rows longer than SEED_LONG: k_seed_choose_long (their choice stays
-    // "none" here and is written there)
+    // longer rows: k_seed_choose_rows (their choice stays "none" here and
+    // is written there)
     wave_append(v < n && p1 && deg > SEED_LONG, (int32_t)v, longs_out, sb.count + 1);
-    unsigned long long longs = __ballot(v < n && p1 && deg > SEED_SHORT && deg <= SEED_LONG);
-    while (longs) {
-      const uint32_t src = (uint32_t)__ffsll((long long)longs) - 1;
-      longs &= longs - 1;
-      const uint32_t b = __shfl(e0, (int)src, WAVE);
-      const uint32_t d = __shfl(deg, (int)src, WAVE);
-      const int32_t vv = (int32_t)(v0 + src);
-      bool l = false;
-      V t = -1;
-      uint32_t kk = NONE;
-      for (uint32_t k0 = 0; k0 < d; k0 += SEED_UNROLL * WAVE) {
+    wave_append(v < n && p1 && deg > SEED_FLAT && deg <= SEED_LONG, (int32_t)v, mids_out, sb.count + 3);
+    uint32_t E;
+    const uint32_t ex = block_excl_scan(v < n && p1 && deg <= SEED_FLAT ? deg : 0u, wsum, &E);
+    epre[tid] = ex;
+    if (tid == BLOCK - 1) epre[BLOCK] = E;
+    ebeg[tid] = e0;
+    kmax[tid] = 0;
+    kidx[tid] = NONE;
+    uint32_t best = NONE;         // this thread's row: the chosen edge index
+    unsigned long long prev = 0;  // and its maximum key before the chunk
+    block_sync();
+    for (uint32_t x0 = 0; x0 < E; x0 += J * BLOCK) {
+      uint32_t slot[J], idx[J];
+      int2 ed[J];
+#pragma unroll
+      for (int j = 0; j < J; j++) {
+        const uint32_t x = x0 + j * BLOCK + tid;
+        const uint32_t xc = x < E ? x : E - 1;
+        const uint32_t sl = find_range(epre, xc);
+        slot[j] = x < E ? sl : (uint32_t)BLOCK;
+        idx[j] = xc - epre[sl];
+        ed[j] = g.edges[ebeg[sl] + idx[j]];
+      }
+      uint8_t fz[J];
+      V fu[J];
+#pragma unroll
+      for (int j = 0; j < J; j++) {
+        fz[j] = sb.forced[ed[j].x];
+        fu[j] = f_zero ? V(0) : f[ed[j].x];
+      }
+      unsigned long long key[J];
+      bool cand[J];
+#pragma unroll
+      for (int j = 0; j < J; j++) {
+        const uint32_t sl = slot[j];
+        const bool loop = ed[j].x == (int32_t)(t * BLOCK + sl) && ed[j].y < 0;
+        V tm = fu[j] - (V)ed[j].y;
+        tm = tm > V(0) ? tm : V(0);
+        cand[j] = sl < (uint32_t)BLOCK && fz[j] != 0;
+        key[j] = ((unsigned long long)loop << 63) | (unsigned long long)(int64_t)tm;
+        bool h = cand[j];
+        unsigned long long k = key[j];
+        wave_seg_fold(h, k, sl, [](unsigned long long a, unsigned long long b) { return a > b; });
+        const uint32_t sprev = __shfl_up(sl, 1, WAVE);
+        if (h && (lane == 0 || sprev != sl))
+          __hip_atomic_fetch_max(&kmax[sl], k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+      block_sync();
+      const unsigned long long km = kmax[tid];  // stable until the next chunk's first barrier
+#pragma unroll
+      for (int j = 0; j < J; j++) {
+        const uint32_t sl = slot[j];
+        bool h = cand[j] && key[j] == kmax[sl < (uint32_t)BLOCK ? sl : 0];
+        uint32_t i = idx[j];
+        wave_seg_fold(h, i, sl, [](uint32_t a, uint32_t b) { return a < b; });
+        const uint32_t sprev = __shfl_up(sl, 1, WAVE);
+        if (h && (lane == 0 || sprev != sl))
+          __hip_atomic_fetch_min(&kidx[sl], i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+      block_sync();
+      const uint32_t ci = kidx[tid];
+      if (ci != NONE) {
+        if (best == NONE || km != prev) best = ci;
+        kidx[tid] = NONE;  // read again only after the next chunk's first barrier
+      }
+      prev = km;
+    }
+    if (v < n) {
+      if (!p1 && deg == 1) best = 0;
+      int32_t to = -1, bw = 0;
+      if (best != NONE) {
+        const int2 ed = g.edges[e0 + best];
+        to = ed.x;
+        bw = ed.y;
+      }
+      sb.succ[v] = to;
+      sb.wgt[v] = bw;
+      sb.pl[0][v] = make_int2(to, (int32_t)v);
+      sb.oncyc[v] = 0;
+      sb.sum[v] = 0;
+    }
+    // the next tile rewrites epre, ebeg, kmax and kidx only after its scan's
+    // barrier, which every thread reaches after its last read of them here
+  }
+}
+
+// sigma1 for the player-1 rows of a list made by k_seed_choose, G threads
+// per row (G = WAVE: a wave per row; G = BLOCK: a block per row),
+// SEED_UNROLL * G edges per step, the same candidate order.
+template <typename V, int G>
+__global__ __launch_bounds__(BLOCK) void k_seed_choose_rows(DevGame g, SeedBuf sb, const int32_t* list,
+                                                            const uint32_t* count, bool f_zero) {
+  __shared__ int s_l[BLOCK / WAVE];
+  __shared__ V s_t[BLOCK / WAVE];
+  __shared__ uint32_t s_k[BLOCK / WAVE];
+  static_assert(G == WAVE || G == BLOCK, "a wave or a block per row");
+  const V* f = (const V*)g.f;
+  const uint32_t tid = threadIdx.x, lane = lane_id(), wid = tid / WAVE;
+  constexpr uint32_t NONE = 0xFFFFFFFFu;
+  constexpr uint32_t ROWS = BLOCK / G;  // rows a block takes at once
+  const uint32_t rank = tid % G;
+  const uint32_t cnt = *count;
+  // the loop bound is uniform over the block; the row index over its group
+  for (uint32_t i0 = blockIdx.x * ROWS; i0 < cnt; i0 += gridDim.x * ROWS) {
+    const uint32_t i = i0 + tid / G;
+    bool l = false;
+    V t = -1;
+    uint32_t kk = NONE, e0 = 0;
+    int32_t v = -1;
+    if (i < cnt) {
+      v = list[i];
+      e0 = g.rs[v] & ROW_MASK;
+      const uint32_t d = (g.rs[v + 1] & ROW_MASK) - e0;
+      for (uint32_t k0 = 0; k0 < d; k0 += SEED_UNROLL * G) {
         int2 ed[SEED_UNROLL];
 #pragma unroll
-        for (int j = 0; j < SEED_UNROLL; j++) ed[j] = g.edges[b + min(k0 + j * WAVE + lane, d - 1)];
+        for (int j = 0; j < SEED_UNROLL; j++) ed[j] = g.edges[e0 + min(k0 + j * G + rank, d - 1)];
         uint8_t fz[SEED_UNROLL];
         V fu[SEED_UNROLL];
 #pragma unroll
         for (int j = 0; j < SEED_UNROLL; j++) {
           fz[j] = sb.forced[ed[j].x];
-          fu[j] = f[ed[j].x];
+          fu[j] = f_zero ? V(0) : f[ed[j].x];
         }
 #pragma unroll
         for (int j = 0; j < SEED_UNROLL; j++) {
-          const uint32_t k = k0 + j * WAVE + lane;
+          const uint32_t k = k0 + j * G + rank;
           if (k >= d || !fz[j]) continue;
-          const bool lj = ed[j].x == vv && ed[j].y < 0;
+          const bool lj = ed[j].x == v && ed[j].y < 0;
           V tm = fu[j] - (V)ed[j].y;
           tm = tm > V(0) ? tm : V(0);
           if (kk == NONE || seed_better<V>(lj, tm, k, l, t, kk)) {
@@ -1790,80 +1897,8 @@ __global__ __launch_bounds__(BLOCK) void k_seed_choose(DevGame g, SeedBuf sb, in
           }
         }
       }
-      // the wave's best candidate (NONE loses to every candidate)
-#pragma unroll
-      for (int o = 1; o < WAVE; o <<= 1) {
-        const bool lo_ = __shfl_xor((int)l, o, WAVE) != 0;
-        const V to = __shfl_xor(t, o, WAVE);
-        const uint32_t ko = __shfl_xor(kk, o, WAVE);
-        if (ko != NONE && (kk == NONE || seed_better<V>(lo_, to, ko, l, t, kk))) {
-          l = lo_;
-          t = to;
-          kk = ko;
-        }
-      }
-      if (lane == src) kbest = kk;
     }
-    if (v < n) {
-      int32_t best = -1, bw = 0;
-      if (kbest != NONE) {
-        const int2 ed = g.edges[e0 + kbest];
-        best = ed.x;
-        bw = ed.y;
-      }
-      sb.succ[v] = best;
-      sb.wgt[v] = bw;
-      sb.p[0][v] = best;
-      sb.lo[0][v] = (int32_t)v;
-      sb.oncyc[v] = 0;
-      sb.sum[v] = 0;
-    }
-  }
-}
-
-// sigma1 for the player-1 rows listed by k_seed_choose (longer than
-// SEED_LONG): one block per row, SEED_UNROLL * BLOCK edges per step, the
-// same candidate order.
-template <typename V>
-__global__ __launch_bounds__(BLOCK) void k_seed_choose_long(DevGame g, SeedBuf sb, const int32_t* list) {
-  __shared__ int s_l[BLOCK / WAVE];
-  __shared__ V s_t[BLOCK / WAVE];
-  __shared__ uint32_t s_k[BLOCK / WAVE];
-  const V* f = (const V*)g.f;
-  const uint32_t tid = threadIdx.x, lane = lane_id(), wid = tid / WAVE;
-  constexpr uint32_t NONE = 0xFFFFFFFFu;
-  const uint32_t cnt = sb.count[1];
-  for (uint32_t i = blockIdx.x; i < cnt; i += gridDim.x) {
-    const int32_t v = list[i];
-    const uint32_t e0 = g.rs[v] & ROW_MASK, d = (g.rs[v + 1] & ROW_MASK) - e0;
-    bool l = false;
-    V t = -1;
-    uint32_t kk = NONE;
-    for (uint32_t k0 = 0; k0 < d; k0 += SEED_UNROLL * BLOCK) {
-      int2 ed[SEED_UNROLL];
-#pragma unroll
-      for (int j = 0; j < SEED_UNROLL; j++) ed[j] = g.edges[e0 + min(k0 + j * BLOCK + tid, d - 1)];
-      uint8_t fz[SEED_UNROLL];
-      V fu[SEED_UNROLL];
-#pragma unroll
-      for (int j = 0; j < SEED_UNROLL; j++) {
-        fz[j] = sb.forced[ed[j].x];
-        fu[j] = f[ed[j].x];
-      }
-#pragma unroll
-      for (int j = 0; j < SEED_UNROLL; j++) {
-        const uint32_t k = k0 + j * BLOCK + tid;
-        if (k >= d || !fz[j]) continue;
-        const bool lj = ed[j].x == v && ed[j].y < 0;
-        V tm = fu[j] - (V)ed[j].y;
-        tm = tm > V(0) ? tm : V(0);
-        if (kk == NONE || seed_better<V>(lj, tm, k, l, t, kk)) {
-          l = lj;
-          t = tm;
-          kk = k;
-        }
-      }
-    }
+    // the wave's best candidate (NONE loses to every candidate)
 #pragma unroll
     for (int o = 1; o < WAVE; o <<= 1) {
       const bool lo_ = __shfl_xor((int)l, o, WAVE) != 0;
@@ -1875,19 +1910,24 @@ __global__ __launch_bounds__(BLOCK) void k_seed_choose_long(DevGame g, SeedBuf s
         kk = ko;
       }
     }
-    if (lane == 0) {
-      s_l[wid] = l;
-      s_t[wid] = t;
-      s_k[wid] = kk;
+    bool writer = lane == 0 && i < cnt;
+    if constexpr (G == BLOCK) {
+      if (lane == 0) {
+        s_l[wid] = l;
+        s_t[wid] = t;
+        s_k[wid] = kk;
+      }
+      block_sync();
+      writer = tid == 0 && i < cnt;
+      if (writer)
+        for (int w = 1; w < BLOCK / WAVE; w++)
+          if (s_k[w] != NONE && (kk == NONE || seed_better<V>(s_l[w] != 0, s_t[w], s_k[w], l, t, kk))) {
+            l = s_l[w] != 0;
+            t = s_t[w];
+            kk = s_k[w];
+          }
     }
-    block_sync();
-    if (tid == 0) {
-      for (int w = 1; w < BLOCK / WAVE; w++)
-        if (s_k[w] != NONE && (kk == NONE || seed_better<V>(s_l[w] != 0, s_t[w], s_k[w], l, t, kk))) {
-          l = s_l[w] != 0;
-          t = s_t[w];
-          kk = s_k[w];
-        }
+    if (writer) {
       int32_t best = -1, bw = 0;
       if (kk != NONE) {
         const int2 ed = g.edges[e0 + kk];
@@ -1896,34 +1936,41 @@ __global__ __launch_bounds__(BLOCK) void k_seed_choose_long(DevGame g, SeedBuf s
       }
       sb.succ[v] = best;
       sb.wgt[v] = bw;
-      sb.p[0][v] = best;
+      sb.pl[0][v].x = best;
     }
-    block_sync();  // the next row rewrites the wave results
+    if constexpr (G == BLOCK) block_sync();  // the next row rewrites the wave results
   }
 }
 
-__global__ void k_seed_jump(int32_t n, const int32_t* p, const int32_t* lo, int32_t* p2, int32_t* lo2) {
+// One doubling step on {pointer, smallest id} pairs (one gather per vertex).
+__global__ void k_seed_jump(int32_t n, const int2* pl, int2* pl2) {
   for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
-    const int32_t u = p[v];
-    p2[v] = u >= 0 ? p[u] : -1;
-    lo2[v] = u >= 0 ? min(lo[v], lo[u]) : lo[v];
+    const int2 a = pl[v];
+    if (a.x >= 0) {
+      const int2 b = pl[a.x];
+      pl2[v] = make_int2(b.x, min(a.y, b.y));
+    } else {
+      pl2[v] = a;
+    }
   }
 }
 
-__global__ void k_seed_mark(int32_t n, const int32_t* p, uint8_t* oncyc) {
-  for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
-    if (p[v] >= 0) oncyc[p[v]] = 1;
+__global__ void k_seed_mark(int32_t n, const int2* pl, uint8_t* oncyc) {
+  for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+    const int32_t u = pl[v].x;
+    if (u >= 0) oncyc[u] = 1;
+  }
 }
 
-__global__ void k_seed_sum(int32_t n, const SeedBuf sb, const int32_t* lo) {
+__global__ void k_seed_sum(int32_t n, const SeedBuf sb, const int2* pl) {
   for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
-    if (sb.oncyc[v]) atomicAdd((unsigned long long*)&sb.sum[lo[v]], (unsigned long long)(long long)sb.wgt[v]);
+    if (sb.oncyc[v]) atomicAdd((unsigned long long*)&sb.sum[pl[v].y], (unsigned long long)(long long)sb.wgt[v]);
 }
 
 // TOP on the vertices of negative cycles; their predecessors join L_r (flags).
 // A short predecessor list is flagged by its lane, a long one by the whole wave.
 template <typename V>
-__global__ __launch_bounds__(BLOCK) void k_seed_apply(DevGame g, const SeedBuf sb, const int32_t* lo, uint32_t r,
+__global__ __launch_bounds__(BLOCK) void k_seed_apply(DevGame g, const SeedBuf sb, const int2* pl, uint32_t r,
                                                       int32_t* longs_out) {
   V* f = (V*)g.f;
   const V top = (V)g.top;
@@ -1936,7 +1983,7 @@ __global__ __launch_bounds__(BLOCK) void k_seed_apply(DevGame g, const SeedBuf s
     const uint32_t v = v0 + lane;
     bool set = false;
     uint32_t pb = 0, pe = 0;
-    if (v < n && sb.oncyc[v] && sb.sum[lo[v]] < 0 && f[v] != top) {
+    if (v < n && sb.oncyc[v] && sb.sum[pl[v].y] < 0 && f[v] != top) {
       f[v] = top;
       mine++;
       set = true;
@@ -1974,17 +2021,20 @@ __global__ __launch_bounds__(BLOCK) void k_seed_apply_long(DevGame g, const Seed
 size_t seed_bytes(int32_t n) {
   const size_t nn = (size_t)n;
   auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
-  return 6 * up(4 * nn) + 2 * up(nn) + up(8 * nn) + up(4);
+  return 2 * up(4 * nn) + 3 * up(8 * nn) + 2 * up(nn) + up(16);
 }
 
 void bind_seed(SeedBuf& sb, void* base, int32_t n) {
   const size_t nn = (size_t)n;
   auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
   char* b = (char*)base;
-  int32_t** a4[6] = {&sb.succ, &sb.wgt, &sb.p[0], &sb.p[1], &sb.lo[0], &sb.lo[1]};
-  for (auto q : a4) {
-    *q = (int32_t*)b;
-    b += up(4 * nn);
+  sb.succ = (int32_t*)b;
+  b += up(4 * nn);
+  sb.wgt = (int32_t*)b;
+  b += up(4 * nn);
+  for (auto& q : sb.pl) {
+    q = (int2*)b;
+    b += up(8 * nn);
   }
   sb.forced = (uint8_t*)b;
   b += up(nn);
@@ -1998,36 +2048,45 @@ void bind_seed(SeedBuf& sb, void* base, int32_t n) {
 // One seeding pass before round r; sb.count receives the number of vertices
 // set to TOP.  When it is nonzero the caller runs round r as a dense round
 // (ctrl[C_ANY0 + (r - 1) % 3] is set here).
-hipError_t launch_seed(const DevGame& g, int vbits, const SeedBuf& sb, uint32_t r, hipStream_t s) {
+hipError_t launch_seed(const DevGame& g, int vbits, const SeedBuf& sb, uint32_t r, bool f_zero, hipStream_t s) {
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(((int64_t)g.n + BLOCK - 1) / BLOCK, 8192));
   // count[0]: vertices set to TOP; count[1], count[2]: long rows and long
-  // predecessor lists handed to the block-per-row kernels
+  // predecessor lists handed to the block-per-row kernels, count[3]: rows
+  // handed to the wave-per-row kernel
   hipError_t e = hipMemsetAsync(sb.count, 0, 16, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_seed_forced, dim3(grid), dim3(BLOCK), 0, s, g, sb);
-  // the long-row list lives in p[1] until the first doubling pass writes it
+  // the long-row list and the medium-row list live in the two halves of
+  // pl[1] until the first doubling pass writes it
+  int32_t* longs = (int32_t*)sb.pl[1];
+  int32_t* mids = longs + g.n;
   if (vbits == 32) {
-    hipLaunchKernelGGL(k_seed_choose<int32_t>, dim3(grid), dim3(BLOCK), 0, s, g, sb, sb.p[1]);
-    hipLaunchKernelGGL(k_seed_choose_long<int32_t>, dim3(SEED_LONG_GRID), dim3(BLOCK), 0, s, g, sb,
-                       (const int32_t*)sb.p[1]);
+    hipLaunchKernelGGL(k_seed_choose<int32_t>, dim3(grid), dim3(BLOCK), 0, s, g, sb, longs, mids, f_zero);
+    hipLaunchKernelGGL((k_seed_choose_rows<int32_t, WAVE>), dim3(SEED_MID_GRID), dim3(BLOCK), 0, s, g, sb,
+                       (const int32_t*)mids, (const uint32_t*)sb.count + 3, f_zero);
+    hipLaunchKernelGGL((k_seed_choose_rows<int32_t, BLOCK>), dim3(SEED_LONG_GRID), dim3(BLOCK), 0, s, g, sb,
+                       (const int32_t*)longs, (const uint32_t*)sb.count + 1, f_zero);
   } else {
-    hipLaunchKernelGGL(k_seed_choose<int64_t>, dim3(grid), dim3(BLOCK), 0, s, g, sb, sb.p[1]);
-    hipLaunchKernelGGL(k_seed_choose_long<int64_t>, dim3(SEED_LONG_GRID), dim3(BLOCK), 0, s, g, sb,
-                       (const int32_t*)sb.p[1]);
+    hipLaunchKernelGGL(k_seed_choose<int64_t>, dim3(grid), dim3(BLOCK), 0, s, g, sb, longs, mids, f_zero);
+    hipLaunchKernelGGL((k_seed_choose_rows<int64_t, WAVE>), dim3(SEED_MID_GRID), dim3(BLOCK), 0, s, g, sb,
+                       (const int32_t*)mids, (const uint32_t*)sb.count + 3, f_zero);
+    hipLaunchKernelGGL((k_seed_choose_rows<int64_t, BLOCK>), dim3(SEED_LONG_GRID), dim3(BLOCK), 0, s, g, sb,
+                       (const int32_t*)longs, (const uint32_t*)sb.count + 1, f_zero);
   }
   int cur = 0;
   for (int64_t span = 1; span <= 2 * (int64_t)g.n; span *= 2, cur ^= 1)
-    hipLaunchKernelGGL(k_seed_jump, dim3(grid), dim3(BLOCK), 0, s, g.n, sb.p[cur], sb.lo[cur], sb.p[cur ^ 1],
-                       sb.lo[cur ^ 1]);
-  hipLaunchKernelGGL(k_seed_mark, dim3(grid), dim3(BLOCK), 0, s, g.n, sb.p[cur], sb.oncyc);
-  hipLaunchKernelGGL(k_seed_sum, dim3(grid), dim3(BLOCK), 0, s, g.n, sb, sb.lo[cur]);
-  // the long-list list lives in p[cur ^ 1], free after the last doubling pass
+    hipLaunchKernelGGL(k_seed_jump, dim3(grid), dim3(BLOCK), 0, s, g.n, (const int2*)sb.pl[cur], sb.pl[cur ^ 1]);
+  hipLaunchKernelGGL(k_seed_mark, dim3(grid), dim3(BLOCK), 0, s, g.n, (const int2*)sb.pl[cur], sb.oncyc);
+  hipLaunchKernelGGL(k_seed_sum, dim3(grid), dim3(BLOCK), 0, s, g.n, sb, (const int2*)sb.pl[cur]);
+  // the long-list list lives in pl[cur ^ 1], free after the last doubling pass
+  int32_t* lists = (int32_t*)sb.pl[cur ^ 1];
   if (vbits == 32)
-    hipLaunchKernelGGL(k_seed_apply<int32_t>, dim3(grid), dim3(BLOCK), 0, s, g, sb, sb.lo[cur], r, sb.p[cur ^ 1]);
+    hipLaunchKernelGGL(k_seed_apply<int32_t>, dim3(grid), dim3(BLOCK), 0, s, g, sb, (const int2*)sb.pl[cur], r,
+                       lists);
   else
-    hipLaunchKernelGGL(k_seed_apply<int64_t>, dim3(grid), dim3(BLOCK), 0, s, g, sb, sb.lo[cur], r, sb.p[cur ^ 1]);
-  hipLaunchKernelGGL(k_seed_apply_long, dim3(SEED_LONG_GRID), dim3(BLOCK), 0, s, g, sb, (const int32_t*)sb.p[cur ^ 1],
-                     r);
+    hipLaunchKernelGGL(k_seed_apply<int64_t>, dim3(grid), dim3(BLOCK), 0, s, g, sb, (const int2*)sb.pl[cur], r,
+                       lists);
+  hipLaunchKernelGGL(k_seed_apply_long, dim3(SEED_LONG_GRID), dim3(BLOCK), 0, s, g, sb, (const int32_t*)lists, r);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   return hipMemsetAsync(g.ctrl + C_ANY0 + (r + 2) % 3, 0xFF, 1, s);
