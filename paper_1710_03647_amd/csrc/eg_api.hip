@@ -807,10 +807,10 @@ static int solve_impl(eg_game* g, const eg_solve_opts* opts, int64_t* credits, e
   auto pick = [&](uint64_t size) { return size <= small_limit ? SMALL : size >= dense_at ? DENSE : SPARSE; };
   int mode = pick(active);
   // Each initially active vertex rises in round 1 (its flag means that its
-  // lift from 0 is positive).  When their predecessors would cover V, the
-  // first rounds lift every vertex instead of flagging predecessors one
-  // store at a time.
-  if (mode == DENSE && !o.resume && !scc && (dg.nparts == 1 || dg.slice_major) &&
+  // lift from 0 is positive; on resume every vertex is active).  When their
+  // predecessors would cover V, the first rounds lift every vertex instead of
+  // flagging predecessors one store at a time.
+  if (mode == DENSE && !scc && (dg.nparts == 1 || dg.slice_major) &&
       (double)active * g->avg_indeg >= (double)g->n)
     mode = ALL;
   if (active && mode != DENSE && mode != ALL) HIPCHK(eg::launch_compact(dg, 1, grid, s));
@@ -864,6 +864,7 @@ static int solve_impl(eg_game* g, const eg_solve_opts* opts, int64_t* credits, e
     }
     uint64_t allowed = 64;
     if (mode == SMALL) allowed = 8192;
+    else if (mode == ALL) allowed = 1;  // each costs a full lift: the next mode is chosen after every one
     else allowed = batch;
     if (max_rounds) allowed = std::min<uint64_t>(allowed, max_rounds - launched);
     HIPCHK(hipEventRecord(g->ev[3], s));

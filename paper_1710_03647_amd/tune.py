@@ -95,20 +95,23 @@ def _time(game, cfg: dict, max_rounds: int, device: int, seeded: bool = False) -
     with eg.Context(device, top_seeding=int(seeded), **cfg) as ctx:
         with ctx.create(game) as g:
             g.solve(max_rounds=min(max_rounds, 50) if max_rounds else 50, allow_timeout=True)  # warm
-            reps = 3 if seeded else 1
-            ts = []
-            for _ in range(reps):
-                t0 = time.perf_counter()
-                g.solve(max_rounds=max_rounds, allow_timeout=True)
-                ts.append(time.perf_counter() - t0)
-            return sorted(ts)[len(ts) // 2]
+            if seeded:
+                # device time of the solve (HIP events around init, seeding and
+                # rounds), median of five: millisecond solves, where the host's
+                # copy of the credits and its jitter would decide the order
+                ts = [g.solve(max_rounds=max_rounds, allow_timeout=True)[1]["t_solve"] for _ in range(5)]
+                return sorted(ts)[len(ts) // 2]
+            t0 = time.perf_counter()
+            g.solve(max_rounds=max_rounds, allow_timeout=True)
+            return time.perf_counter() - t0
 
 
 def tune(game, device: int = 0, path: str = TABLE, space: dict | None = None, verbose: bool = True,
          seeded: bool = False) -> dict:
     """Time every candidate on the proxy, store and return the fastest.  With
     seeded = True the candidates are timed on seeded solves of the game itself
-    (median of three; these take milliseconds where seeding finds the traps)."""
+    (device time, median of five; these take milliseconds where seeding finds
+    the traps)."""
     from . import eg
 
     space = space or SPACE
