@@ -918,7 +918,8 @@ static int solve_impl(eg_game* g, const eg_solve_opts* opts, int64_t* credits, e
       const double est = (double)changed * g->avg_indeg;
       wide = est >= (double)g->n / 2;
       if (mode == ALL) {
-        if (est < (double)g->n / 2) next_mode = DENSE;
+        // (a list round would give a hub's row to one block; flag rounds cut it)
+        if (est < (double)g->n / 2) next_mode = est <= (double)small_limit ? SMALL : DENSE;
       } else if (est >= (double)g->n && (dg.nparts == 1 || dg.slice_major) && !scc) {
         next_mode = ALL;
       } else if (est <= (double)small_limit) {
@@ -941,12 +942,13 @@ static int solve_impl(eg_game* g, const eg_solve_opts* opts, int64_t* credits, e
     if (next_mode != mode) {
       if (mode == DENSE && next_mode != ALL) HIPCHK(eg::launch_compact(dg, r, grid, s));
       if (mode == ALL) {
-        // ALL rounds activate nothing: the round that follows lifts every
-        // vertex again, this time activating the predecessors of changes
+        // ALL rounds activate nothing but flag the vertices they raise: the
+        // predecessors of the last one's raises form L_r, as a dense round
+        // would have flagged them
         uint8_t* act_r = (r & 1) ? dg.act1 : dg.act0;
-        uint8_t* act_n = (r & 1) ? dg.act0 : dg.act1;
-        HIPCHK(hipMemsetAsync(act_r, 1, (size_t)g->n, s));
-        HIPCHK(hipMemsetAsync(act_n, 0, (size_t)g->n, s));
+        HIPCHK(hipMemsetAsync(act_r, 0, (size_t)g->n, s));
+        HIPCHK(eg::launch_activate_changed(dg, g->vbits, r, grid, s));
+        if (next_mode != DENSE) HIPCHK(eg::launch_compact(dg, r, grid, s));
       }
       mode = next_mode;
       batch = 2;

@@ -253,6 +253,10 @@ size_t scan_tmp_words(size_t count);
 // Solve steps
 constexpr int TILE_VERTICES = 256;  // vertices (or list entries) per block tile
 hipError_t launch_init(const DevGame& g, int vbits, int resume, int grid, hipStream_t s);
+// After all-vertex rounds up to r - 1: the predecessors of the vertices raised
+// in round r - 1 are flagged for round r (whose flags must be zero), and the
+// raise flags cleared.
+hipError_t launch_activate_changed(const DevGame& g, int vbits, uint32_t r, int grid, hipStream_t s);
 hipError_t launch_compact(const DevGame& g, uint32_t r, int grid, hipStream_t s);
 hipError_t launch_round(const DevGame& g, int vbits, int h, bool dense, uint32_t r, int grid, hipStream_t s);
 hipError_t launch_reduce_stats(const DevGame& g, int nblocks, hipStream_t s);

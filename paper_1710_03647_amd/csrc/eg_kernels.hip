@@ -1139,6 +1139,10 @@ __device__ __forceinline__ void round_tile(const DevGame& g, RoundShared<V>& sh,
       c.changes++;
       ideg = pe - pb;
     }
+    // all-vertex rounds leave a flag on each vertex they raise, in their own
+    // (otherwise unused) flag array: k_activate_changed turns the last one's
+    // flags into the next active set
+    if (ALL) act_cur[v] = nv != old ? 1 : 0;
   }
   if (ALL) return;
   uint32_t P;
@@ -1287,10 +1291,11 @@ __device__ __forceinline__ void round_seg(const DevGame& g, RoundShared<V>& sh, 
   uint32_t ideg = 0;
   V nval = 0;
   if (v >= 0) {
-    if (!ALL) act_cur[v] = 0;  // consumed
     V nv = (raw & OWNER_BIT) ? -k : k;
     if (nv > bound) nv = top;
     if (nv < old) nv = old;  // writes never lower a value (see round_tile)
+    // consumed; all-vertex rounds flag the vertices they raise (see round_tile)
+    act_cur[v] = ALL && nv != old ? 1 : 0;
     if (was_active) {
       c.lifts++;
       c.edges += deg;
@@ -1535,6 +1540,52 @@ __device__ __forceinline__ void block_counters(RoundShared<V>& sh, const Counter
   atomicAdd(&sh.st[S_SCANNED], c.scanned);
   atomicAdd(&sh.st[S_FILTERED], c.filtered);
   block_sync();
+}
+
+// After all-vertex rounds: the predecessors of the vertices that the last one
+// (round r - 1) raised join L_r (flags of round r, cleared by the caller), with
+// the same predecessor scan and filter as the end of a dense round; the raise
+// flags are cleared for the flags of round r + 1.
+template <typename V>
+__global__ __launch_bounds__(BLOCK) void k_activate_changed(DevGame g, uint32_t r) {
+  __shared__ RoundShared<V> sh;
+  const uint32_t tid = threadIdx.x;
+  uint8_t* raised = (r & 1) ? g.act0 : g.act1;  // flags of round r - 1 (= r + 1)
+  uint8_t* act_next = (r & 1) ? g.act1 : g.act0;
+  const V* f = (const V*)g.f;
+  if (tid < S_WORDS) sh.st[tid] = 0;
+  Counters c;
+  const uint32_t ntiles = ((uint32_t)g.n + TILE - 1) / TILE;
+  for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const uint32_t v = t * TILE + tid;
+    uint32_t ideg = 0, pb = 0;
+    V val = 0;
+    if (v < (uint32_t)g.n && raised[v]) {
+      raised[v] = 0;
+      pb = g.rev_off[v];
+      ideg = g.rev_off[v + 1] - pb;
+      val = f[v];
+    }
+    uint32_t P;
+    const uint32_t pex = block_excl_scan(ideg, sh.wsum, &P);  // also orders the previous tile's reads
+    sh.ppre[tid] = pex;
+    if (tid == BLOCK - 1) sh.ppre[BLOCK] = P;
+    sh.pbeg[tid] = pb;
+    sh.pval[tid] = val;
+    c.scanned += ideg;
+    block_sync();
+    for (uint32_t x0 = 0; x0 < P; x0 += BLOCK * UNROLL) {
+      switch (std::min<uint32_t>((P - x0 + BLOCK - 1) / BLOCK, UNROLL)) {
+        case 1: scan_preds<true, V, 1>(g, sh, x0, P, act_next, nullptr, nullptr, c.pushes, c.filtered); break;
+        case 2: scan_preds<true, V, 2>(g, sh, x0, P, act_next, nullptr, nullptr, c.pushes, c.filtered); break;
+        case 3: scan_preds<true, V, 3>(g, sh, x0, P, act_next, nullptr, nullptr, c.pushes, c.filtered); break;
+        default: scan_preds<true, V, UNROLL>(g, sh, x0, P, act_next, nullptr, nullptr, c.pushes, c.filtered); break;
+      }
+    }
+    block_sync();  // the next tile rewrites ppre, pbeg and pval
+  }
+  block_counters(sh, c);
+  if (tid < S_WORDS) g.slots[blockIdx.x * S_WORDS + tid] += sh.st[tid];
 }
 
 // One round of Alg. 3 over L_r of one game: blocks take the tiles of the
@@ -2343,6 +2394,12 @@ static int vertex_grid(const DevGame& g, int max_grid) {
 hipError_t launch_init(const DevGame& g, int vbits, int resume, int grid, hipStream_t s) {
   if (vbits == 32) hipLaunchKernelGGL(k_init<int32_t>, dim3(grid), dim3(BLOCK), 0, s, g, resume);
   else hipLaunchKernelGGL(k_init<int64_t>, dim3(grid), dim3(BLOCK), 0, s, g, resume);
+  return hipGetLastError();
+}
+
+hipError_t launch_activate_changed(const DevGame& g, int vbits, uint32_t r, int grid, hipStream_t s) {
+  if (vbits == 32) hipLaunchKernelGGL(k_activate_changed<int32_t>, dim3(grid), dim3(BLOCK), 0, s, g, r);
+  else hipLaunchKernelGGL(k_activate_changed<int64_t>, dim3(grid), dim3(BLOCK), 0, s, g, r);
   return hipGetLastError();
 }
 
