@@ -1993,6 +1993,109 @@ __global__ __launch_bounds__(BLOCK) void k_seed_choose_rows(DevGame g, SeedBuf s
   }
 }
 
+// sigma1 for the player-1 rows longer than SEED_LONG (few, but the largest
+// would hold one block for its whole length): each row is cut into
+// SEED_PIECES pieces, one block per piece, in two passes over the pieces
+// and a closing one over the rows.  PHASE 0 folds each piece's best
+// (negative self-loop, term) key into the row's 64-bit maximum (in the
+// per-cycle sum array, zero until the doubling ends); PHASE 1 folds the
+// lowest edge index among the candidates holding that maximum into the row's
+// entry of succ (NONE from k_seed_choose); k_seed_choose_close turns the index
+// into the chosen edge and clears the maximum.  The order is the same as in
+// the other choice kernels.
+constexpr uint32_t SEED_PIECES = 16;
+
+template <typename V, int PHASE>
+__global__ __launch_bounds__(BLOCK) void k_seed_choose_pieces(DevGame g, SeedBuf sb, const int32_t* list,
+                                                              const uint32_t* count, bool f_zero) {
+  __shared__ unsigned long long s_key[BLOCK / WAVE];
+  __shared__ uint32_t s_has[BLOCK / WAVE];
+  const V* f = (const V*)g.f;
+  constexpr uint32_t NONE = 0xFFFFFFFFu;
+  const uint32_t tid = threadIdx.x, lane = lane_id(), wid = tid / WAVE;
+  const uint32_t total = *count * SEED_PIECES;
+  for (uint32_t x = blockIdx.x; x < total; x += gridDim.x) {  // block-uniform
+    const int32_t v = list[x / SEED_PIECES];
+    const uint32_t j = x % SEED_PIECES;
+    const uint32_t e0 = g.rs[v] & ROW_MASK, d = (g.rs[v + 1] & ROW_MASK) - e0;
+    const uint32_t lo = (uint32_t)((uint64_t)d * j / SEED_PIECES), hi = (uint32_t)((uint64_t)d * (j + 1) / SEED_PIECES);
+    const unsigned long long target = PHASE == 1 ? (unsigned long long)sb.sum[v] : 0ull;
+    bool has = false;
+    unsigned long long best = 0;  // PHASE 0: the largest key; PHASE 1: the lowest index holding the target
+    for (uint32_t k0 = lo; k0 < hi; k0 += SEED_UNROLL * BLOCK) {
+      int2 ed[SEED_UNROLL];
+#pragma unroll
+      for (int q = 0; q < SEED_UNROLL; q++) ed[q] = g.edges[e0 + min(k0 + q * BLOCK + tid, hi - 1)];
+      uint8_t fz[SEED_UNROLL];
+      V fu[SEED_UNROLL];
+#pragma unroll
+      for (int q = 0; q < SEED_UNROLL; q++) {
+        fz[q] = sb.forced[ed[q].x];
+        fu[q] = f_zero ? V(0) : f[ed[q].x];
+      }
+#pragma unroll
+      for (int q = 0; q < SEED_UNROLL; q++) {
+        const uint32_t k = k0 + q * BLOCK + tid;
+        if (k >= hi || !fz[q]) continue;
+        V tm = fu[q] - (V)ed[q].y;
+        tm = tm > V(0) ? tm : V(0);
+        const unsigned long long key =
+            ((unsigned long long)(ed[q].x == v && ed[q].y < 0) << 63) | (unsigned long long)(int64_t)tm;
+        if (PHASE == 0) {
+          if (!has || key > best) best = key;
+          has = true;
+        } else if (key == target) {
+          if (!has || k < best) best = k;
+          has = true;
+        }
+      }
+    }
+    // the block's fold: largest key (PHASE 0) or lowest index (PHASE 1)
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+      const unsigned long long bo = __shfl_xor(best, o, WAVE);
+      const bool ho = __shfl_xor((int)has, o, WAVE) != 0;
+      if (ho && (!has || (PHASE == 0 ? bo > best : bo < best))) best = bo;
+      has = has || ho;
+    }
+    if (lane == 0) {
+      s_key[wid] = best;
+      s_has[wid] = has;
+    }
+    block_sync();
+    if (tid == 0) {
+      for (int w = 1; w < BLOCK / WAVE; w++)
+        if (s_has[w] && (!has || (PHASE == 0 ? s_key[w] > best : s_key[w] < best))) {
+          best = s_key[w];
+          has = true;
+        }
+      if (has) {
+        if (PHASE == 0) atomicMax((unsigned long long*)&sb.sum[v], best);
+        else atomicMin((uint32_t*)&sb.succ[v], (uint32_t)best);
+      }
+    }
+    block_sync();  // the next piece rewrites s_key and s_has
+  }
+}
+
+__global__ void k_seed_choose_close(DevGame g, SeedBuf sb, const int32_t* list, const uint32_t* count) {
+  const uint32_t cnt = *count;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += gridDim.x * blockDim.x) {
+    const int32_t v = list[i];
+    const uint32_t k = (uint32_t)sb.succ[v];
+    int32_t to = -1, bw = 0;
+    if (k != 0xFFFFFFFFu) {
+      const int2 ed = g.edges[(g.rs[v] & ROW_MASK) + k];
+      to = ed.x;
+      bw = ed.y;
+    }
+    sb.succ[v] = to;
+    sb.wgt[v] = bw;
+    sb.pl[0][v].x = to;
+    sb.sum[v] = 0;
+  }
+}
+
 // One doubling step on {pointer, smallest id} pairs (one gather per vertex).
 __global__ void k_seed_jump(int32_t n, const int2* pl, int2* pl2) {
   for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
@@ -2056,16 +2159,23 @@ __global__ __launch_bounds__(BLOCK) void k_seed_apply(DevGame g, const SeedBuf s
   if (mine) atomicAdd(sb.count, mine);
 }
 
-// The predecessors of the TOP vertices listed by k_seed_apply join L_r: one
-// block per list.
+// The predecessors of the TOP vertices listed by k_seed_apply join L_r: the
+// grid splits into groups of gridDim / cnt blocks (at least one), and a group
+// flags one list at a time, so that a few hubs with long lists are spread
+// over the whole grid.
 __global__ __launch_bounds__(BLOCK) void k_seed_apply_long(DevGame g, const SeedBuf sb, const int32_t* list,
                                                            uint32_t r) {
   uint8_t* act = (r & 1) ? g.act1 : g.act0;
   const uint32_t cnt = sb.count[2];
-  for (uint32_t i = blockIdx.x; i < cnt; i += gridDim.x) {
+  if (cnt == 0) return;
+  const uint32_t per = max(1u, gridDim.x / cnt);  // blocks per list
+  const uint32_t groups = gridDim.x / per;
+  const uint32_t grp = blockIdx.x / per, part = blockIdx.x % per;
+  if (grp >= groups) return;
+  for (uint32_t i = grp; i < cnt; i += groups) {
     const int32_t v = list[i];
     const uint32_t pb = g.rev_off[v], pe = g.rev_off[v + 1];
-    for (uint32_t k = pb + threadIdx.x; k < pe; k += BLOCK) act[g.rev_src[k]] = 1;
+    for (uint32_t k = pb + part * BLOCK + threadIdx.x; k < pe; k += per * BLOCK) act[g.rev_src[k]] = 1;
   }
 }
 
@@ -2115,15 +2225,21 @@ hipError_t launch_seed(const DevGame& g, int vbits, const SeedBuf& sb, uint32_t 
     hipLaunchKernelGGL(k_seed_choose<int32_t>, dim3(grid), dim3(BLOCK), 0, s, g, sb, longs, mids, f_zero);
     hipLaunchKernelGGL((k_seed_choose_rows<int32_t, WAVE>), dim3(SEED_MID_GRID), dim3(BLOCK), 0, s, g, sb,
                        (const int32_t*)mids, (const uint32_t*)sb.count + 3, f_zero);
-    hipLaunchKernelGGL((k_seed_choose_rows<int32_t, BLOCK>), dim3(SEED_LONG_GRID), dim3(BLOCK), 0, s, g, sb,
+    hipLaunchKernelGGL((k_seed_choose_pieces<int32_t, 0>), dim3(SEED_LONG_GRID), dim3(BLOCK), 0, s, g, sb,
+                       (const int32_t*)longs, (const uint32_t*)sb.count + 1, f_zero);
+    hipLaunchKernelGGL((k_seed_choose_pieces<int32_t, 1>), dim3(SEED_LONG_GRID), dim3(BLOCK), 0, s, g, sb,
                        (const int32_t*)longs, (const uint32_t*)sb.count + 1, f_zero);
   } else {
     hipLaunchKernelGGL(k_seed_choose<int64_t>, dim3(grid), dim3(BLOCK), 0, s, g, sb, longs, mids, f_zero);
     hipLaunchKernelGGL((k_seed_choose_rows<int64_t, WAVE>), dim3(SEED_MID_GRID), dim3(BLOCK), 0, s, g, sb,
                        (const int32_t*)mids, (const uint32_t*)sb.count + 3, f_zero);
-    hipLaunchKernelGGL((k_seed_choose_rows<int64_t, BLOCK>), dim3(SEED_LONG_GRID), dim3(BLOCK), 0, s, g, sb,
+    hipLaunchKernelGGL((k_seed_choose_pieces<int64_t, 0>), dim3(SEED_LONG_GRID), dim3(BLOCK), 0, s, g, sb,
+                       (const int32_t*)longs, (const uint32_t*)sb.count + 1, f_zero);
+    hipLaunchKernelGGL((k_seed_choose_pieces<int64_t, 1>), dim3(SEED_LONG_GRID), dim3(BLOCK), 0, s, g, sb,
                        (const int32_t*)longs, (const uint32_t*)sb.count + 1, f_zero);
   }
+  hipLaunchKernelGGL(k_seed_choose_close, dim3(SEED_LONG_GRID / 4), dim3(BLOCK), 0, s, g, sb, (const int32_t*)longs,
+                     (const uint32_t*)sb.count + 1);
   int cur = 0;
   for (int64_t span = 1; span <= 2 * (int64_t)g.n; span *= 2, cur ^= 1)
     hipLaunchKernelGGL(k_seed_jump, dim3(grid), dim3(BLOCK), 0, s, g.n, (const int2*)sb.pl[cur], sb.pl[cur ^ 1]);

@@ -243,6 +243,12 @@ bool Server::init_device(std::string* why) {
   if ((e = hipHostMalloc((void**)&h_st, 8 * S_WORDS * ns, hipHostMallocDefault))) return bad("pinned", e);
   slot_ticket.assign(ns, nullptr);
   for (int i = nslots - 1; i >= 0; i--) free_slots.push_back(i);
+  // Every epoch graph the worker uses (1, 2, 4, ..., 64 epochs) is captured
+  // here, on the creating thread and before the worker starts: HIP refuses a
+  // device-wide synchronization on any thread while some stream captures, so
+  // a capture on the worker could fail the caller's own calls.
+  for (int k = 1; k <= 64; k *= 2)
+    if (!graph_for(k)) return bad("epoch graph capture", hipErrorUnknown);
   return true;
 }
 

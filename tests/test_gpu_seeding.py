@@ -107,3 +107,47 @@ def test_seeding_hub_rows(sctx, oracle_mod):
     game = synth.make_game(n, edges, owner, W=20, name="hub-rows")
     f, st = seeded_solve(sctx, game)
     pins.expect_equal(f, oracle_mod.solve(game).f, "hub rows")
+
+
+def choice_game(deg, mode):
+    """Player-1 vertex 0 with `deg` out-edges, all into vertices that are not
+    forced (player 0 with two edges: they never enter sigma1) except a few
+    that pin the candidate order of sigma1 (see the caller).  Rows up to 64
+    edges are chosen flattened per tile, longer ones a wave per row, and rows
+    above 2048 edges in pieces over several blocks."""
+    a, b = 1, 2                  # player 1, one edge each back to vertex 0
+    fill0 = 3                    # fillers: player 0, two edges each
+    nfill = 64
+    n = fill0 + nfill
+    pa, pb, ps = int(0.6 * deg), int(0.9 * deg), int(0.8 * deg)
+    row = []
+    for k in range(deg):
+        if k == pa and mode == "tie":
+            row.append((a, -7))          # term 7, the first of two equal largest terms
+        elif k == pb:
+            row.append((b, -7))          # term 7 (in "selfloop": the largest term)
+        elif k == ps and mode == "selfloop":
+            row.append((0, -1))          # negative self-loop, term 1
+        else:
+            row.append((fill0 + k % nfill, 0))
+    edges = [(0, t, w) for t, w in row]
+    edges += [(a, 0, -1), (b, 0, 100)]   # 0 -> a -> 0 sums to -8, 0 -> b -> 0 to 93
+    for i in range(nfill):
+        v = fill0 + i
+        edges += [(v, v, 0), (v, fill0 + (i + 1) % nfill, 1)]
+    owner = [1, 1, 1] + [0] * nfill
+    return synth.make_game(n, edges, owner, W=100, name=f"choice-{mode}-{deg}")
+
+
+@pytest.mark.parametrize("deg", [50, 1500, 5000, 40000])
+@pytest.mark.parametrize("mode", ["tie", "selfloop"])
+def test_seeding_candidate_order_in_every_row_path(sctx, oracle_mod, deg, mode):
+    """sigma1's order decides what the first pass proves.  "tie": two edges
+    share the largest term and only the first (lower index) closes a
+    negative cycle, so exactly {0, a} are seeded.  "selfloop": a negative
+    self-loop beats an edge with a larger term whose cycle is positive, so
+    exactly {0} is seeded.  Every row length path of the choice is used."""
+    game = choice_game(deg, mode)
+    f, st = seeded_solve(sctx, game)
+    pins.expect_equal(f, oracle_mod.solve(game).f, game.name)
+    assert st["seeded"] == (2 if mode == "tie" else 1), (game.name, st["seeded"])
