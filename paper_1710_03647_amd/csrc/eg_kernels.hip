@@ -1807,8 +1807,9 @@ __global__ __launch_bounds__(BLOCK) void k_seed_choose(DevGame g, SeedBuf sb, in
       deg = (g.rs[v + 1] & ROW_MASK) - e0;
       p1 = (a & OWNER_BIT) != 0;
     }
-    // longer rows: k_seed_choose_rows (their choice stays "none" here and
-    // is written there)
+    // longer rows: k_seed_choose_rows up to SEED_LONG edges, then
+    // k_seed_choose_pieces (their choice stays "none" here and is written
+    // there)
     wave_append(v < n && p1 && deg > SEED_LONG, (int32_t)v, longs_out, sb.count + 1);
     wave_append(v < n && p1 && deg > SEED_FLAT && deg <= SEED_LONG, (int32_t)v, mids_out, sb.count + 3);
     uint32_t E;
@@ -1896,56 +1897,47 @@ __global__ __launch_bounds__(BLOCK) void k_seed_choose(DevGame g, SeedBuf sb, in
   }
 }
 
-// sigma1 for the player-1 rows of a list made by k_seed_choose, G threads
-// per row (G = WAVE: a wave per row; G = BLOCK: a block per row),
-// SEED_UNROLL * G edges per step, the same candidate order.
-template <typename V, int G>
+// sigma1 for the player-1 rows of SEED_FLAT + 1 to SEED_LONG edges listed by
+// k_seed_choose: a wave per row, SEED_UNROLL * WAVE edges per step, the same
+// candidate order.
+template <typename V>
 __global__ __launch_bounds__(BLOCK) void k_seed_choose_rows(DevGame g, SeedBuf sb, const int32_t* list,
                                                             const uint32_t* count, bool f_zero) {
-  __shared__ int s_l[BLOCK / WAVE];
-  __shared__ V s_t[BLOCK / WAVE];
-  __shared__ uint32_t s_k[BLOCK / WAVE];
-  static_assert(G == WAVE || G == BLOCK, "a wave or a block per row");
   const V* f = (const V*)g.f;
-  const uint32_t tid = threadIdx.x, lane = lane_id(), wid = tid / WAVE;
+  const uint32_t lane = lane_id();
   constexpr uint32_t NONE = 0xFFFFFFFFu;
-  constexpr uint32_t ROWS = BLOCK / G;  // rows a block takes at once
-  const uint32_t rank = tid % G;
   const uint32_t cnt = *count;
-  // the loop bound is uniform over the block; the row index over its group
-  for (uint32_t i0 = blockIdx.x * ROWS; i0 < cnt; i0 += gridDim.x * ROWS) {
-    const uint32_t i = i0 + tid / G;
+  const uint32_t waves = gridDim.x * (BLOCK / WAVE);
+  // the loop bound is uniform over the wave
+  for (uint32_t i = blockIdx.x * (BLOCK / WAVE) + threadIdx.x / WAVE; i < cnt; i += waves) {
+    const int32_t v = list[i];
+    const uint32_t e0 = g.rs[v] & ROW_MASK;
+    const uint32_t d = (g.rs[v + 1] & ROW_MASK) - e0;
     bool l = false;
     V t = -1;
-    uint32_t kk = NONE, e0 = 0;
-    int32_t v = -1;
-    if (i < cnt) {
-      v = list[i];
-      e0 = g.rs[v] & ROW_MASK;
-      const uint32_t d = (g.rs[v + 1] & ROW_MASK) - e0;
-      for (uint32_t k0 = 0; k0 < d; k0 += SEED_UNROLL * G) {
-        int2 ed[SEED_UNROLL];
+    uint32_t kk = NONE;
+    for (uint32_t k0 = 0; k0 < d; k0 += SEED_UNROLL * WAVE) {
+      int2 ed[SEED_UNROLL];
 #pragma unroll
-        for (int j = 0; j < SEED_UNROLL; j++) ed[j] = g.edges[e0 + min(k0 + j * G + rank, d - 1)];
-        uint8_t fz[SEED_UNROLL];
-        V fu[SEED_UNROLL];
+      for (int j = 0; j < SEED_UNROLL; j++) ed[j] = g.edges[e0 + min(k0 + j * WAVE + lane, d - 1)];
+      uint8_t fz[SEED_UNROLL];
+      V fu[SEED_UNROLL];
 #pragma unroll
-        for (int j = 0; j < SEED_UNROLL; j++) {
-          fz[j] = sb.forced[ed[j].x];
-          fu[j] = f_zero ? V(0) : f[ed[j].x];
-        }
+      for (int j = 0; j < SEED_UNROLL; j++) {
+        fz[j] = sb.forced[ed[j].x];
+        fu[j] = f_zero ? V(0) : f[ed[j].x];
+      }
 #pragma unroll
-        for (int j = 0; j < SEED_UNROLL; j++) {
-          const uint32_t k = k0 + j * G + rank;
-          if (k >= d || !fz[j]) continue;
-          const bool lj = ed[j].x == v && ed[j].y < 0;
-          V tm = fu[j] - (V)ed[j].y;
-          tm = tm > V(0) ? tm : V(0);
-          if (kk == NONE || seed_better<V>(lj, tm, k, l, t, kk)) {
-            l = lj;
-            t = tm;
-            kk = k;
-          }
+      for (int j = 0; j < SEED_UNROLL; j++) {
+        const uint32_t k = k0 + j * WAVE + lane;
+        if (k >= d || !fz[j]) continue;
+        const bool lj = ed[j].x == v && ed[j].y < 0;
+        V tm = fu[j] - (V)ed[j].y;
+        tm = tm > V(0) ? tm : V(0);
+        if (kk == NONE || seed_better<V>(lj, tm, k, l, t, kk)) {
+          l = lj;
+          t = tm;
+          kk = k;
         }
       }
     }
@@ -1961,24 +1953,7 @@ __global__ __launch_bounds__(BLOCK) void k_seed_choose_rows(DevGame g, SeedBuf s
         kk = ko;
       }
     }
-    bool writer = lane == 0 && i < cnt;
-    if constexpr (G == BLOCK) {
-      if (lane == 0) {
-        s_l[wid] = l;
-        s_t[wid] = t;
-        s_k[wid] = kk;
-      }
-      block_sync();
-      writer = tid == 0 && i < cnt;
-      if (writer)
-        for (int w = 1; w < BLOCK / WAVE; w++)
-          if (s_k[w] != NONE && (kk == NONE || seed_better<V>(s_l[w] != 0, s_t[w], s_k[w], l, t, kk))) {
-            l = s_l[w] != 0;
-            t = s_t[w];
-            kk = s_k[w];
-          }
-    }
-    if (writer) {
+    if (lane == 0) {
       int32_t best = -1, bw = 0;
       if (kk != NONE) {
         const int2 ed = g.edges[e0 + kk];
@@ -1989,7 +1964,6 @@ __global__ __launch_bounds__(BLOCK) void k_seed_choose_rows(DevGame g, SeedBuf s
       sb.wgt[v] = bw;
       sb.pl[0][v].x = best;
     }
-    if constexpr (G == BLOCK) block_sync();  // the next row rewrites the wave results
   }
 }
 
@@ -2223,7 +2197,7 @@ hipError_t launch_seed(const DevGame& g, int vbits, const SeedBuf& sb, uint32_t 
   int32_t* mids = longs + g.n;
   if (vbits == 32) {
     hipLaunchKernelGGL(k_seed_choose<int32_t>, dim3(grid), dim3(BLOCK), 0, s, g, sb, longs, mids, f_zero);
-    hipLaunchKernelGGL((k_seed_choose_rows<int32_t, WAVE>), dim3(SEED_MID_GRID), dim3(BLOCK), 0, s, g, sb,
+    hipLaunchKernelGGL(k_seed_choose_rows<int32_t>, dim3(SEED_MID_GRID), dim3(BLOCK), 0, s, g, sb,
                        (const int32_t*)mids, (const uint32_t*)sb.count + 3, f_zero);
     hipLaunchKernelGGL((k_seed_choose_pieces<int32_t, 0>), dim3(SEED_LONG_GRID), dim3(BLOCK), 0, s, g, sb,
                        (const int32_t*)longs, (const uint32_t*)sb.count + 1, f_zero);
@@ -2231,7 +2205,7 @@ hipError_t launch_seed(const DevGame& g, int vbits, const SeedBuf& sb, uint32_t 
                        (const int32_t*)longs, (const uint32_t*)sb.count + 1, f_zero);
   } else {
     hipLaunchKernelGGL(k_seed_choose<int64_t>, dim3(grid), dim3(BLOCK), 0, s, g, sb, longs, mids, f_zero);
-    hipLaunchKernelGGL((k_seed_choose_rows<int64_t, WAVE>), dim3(SEED_MID_GRID), dim3(BLOCK), 0, s, g, sb,
+    hipLaunchKernelGGL(k_seed_choose_rows<int64_t>, dim3(SEED_MID_GRID), dim3(BLOCK), 0, s, g, sb,
                        (const int32_t*)mids, (const uint32_t*)sb.count + 3, f_zero);
     hipLaunchKernelGGL((k_seed_choose_pieces<int64_t, 0>), dim3(SEED_LONG_GRID), dim3(BLOCK), 0, s, g, sb,
                        (const int32_t*)longs, (const uint32_t*)sb.count + 1, f_zero);
