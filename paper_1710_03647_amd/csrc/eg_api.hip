@@ -818,7 +818,7 @@ static int solve_impl(eg_game* g, const eg_solve_opts* opts, int64_t* credits, e
   uint32_t batch = 2;
   double t_kernels = 0;  // device time of the round kernels (back to back within a batch)
   double t_seed = 0;     // device time of the seeding passes
-  uint64_t dense_rounds = 0, all_rounds = 0;
+  uint64_t dense_rounds = 0, all_rounds = 0, all_streak = 0;
   const bool seeding = fixed_sb || ctx->cfg.top_seeding != 0;
   if (fixed_sb) {
     g->sb = *fixed_sb;
@@ -864,7 +864,10 @@ static int solve_impl(eg_game* g, const eg_solve_opts* opts, int64_t* credits, e
     }
     uint64_t allowed = 64;
     if (mode == SMALL) allowed = 8192;
-    else if (mode == ALL) allowed = 1;  // each costs a full lift: the next mode is chosen after every one
+    // All-vertex rounds each cost a full lift, and a batch may overshoot the
+    // end of the phase: one at a time at first, then batches of half the
+    // phase so far (long phases, as on the uniform game, pay few syncs).
+    else if (mode == ALL) allowed = std::min<uint64_t>(64, std::max<uint64_t>(1, all_streak / 2));
     else allowed = batch;
     if (max_rounds) allowed = std::min<uint64_t>(allowed, max_rounds - launched);
     HIPCHK(hipEventRecord(g->ev[3], s));
@@ -901,10 +904,12 @@ static int solve_impl(eg_game* g, const eg_solve_opts* opts, int64_t* credits, e
       const uint32_t next_r = g->h_ctrl[eg::C_NEXT];
       launched += next_r - r;
       r = next_r;
+      all_streak = 0;
     } else {
       launched += allowed;
       dense_rounds += mode == DENSE || mode == ALL ? allowed : 0;
       all_rounds += mode == ALL ? allowed : 0;
+      all_streak = mode == ALL ? all_streak + allowed : 0;
     }
     int next_mode = mode;
     if (mode == DENSE || mode == ALL) {
