@@ -88,8 +88,15 @@ typedef struct {
                                 (Lemma 1): eg_solve runs such a pass before the first round and again
                                 at doubling round counts; serving (eg_submit, eg_solve_batch) runs one
                                 before each game's first round (its device footprint then includes
-                                34 bytes per vertex of scratch).  Exact: the credits do not change,
-                                only the work */
+                                34 bytes per vertex of scratch).  The pass follows one chosen edge per
+                                player-1 vertex (the largest term).  k in 2..64 = eg_solve's passes
+                                first run k Bellman-Ford passes over the forced subgraph (player-1
+                                vertices and out-degree-1 player-0 vertices, values from f, one more
+                                value per vertex of device memory), so that the choice follows the
+                                best paths found and finds negative cycles off the first choice;
+                                values above B also prove TOP.  Serving and
+                                eg_solve_seeded_noalloc run the one-choice pass.  Exact: the credits
+                                do not change, only the work (0..64) */
   int seg_edges;             /* launch shape: dense rounds cut a tile of 256 vertices whose out-degrees
                                 sum above this into segments taken by different blocks: 8192
                                 (0 = default, -1 = never cut; else >= 256) */

@@ -159,6 +159,7 @@ struct eg_game {
   unsigned long long* h_stats = nullptr;
   hipEvent_t ev[6] = {};
   void* seed_mem = nullptr;  // TOP-seeding scratch, allocated by the first seeding solve
+  void* fbf_mem = nullptr;   // values of the Bellman-Ford seeding passes (top_seeding > 1)
   void* seg_mem = nullptr;   // segment tables and combined keys of edge-balanced dense rounds
   void* perm_mem = nullptr;  // internal id of each caller vertex (renumbered games)
   eg::SeedBuf sb{};
@@ -213,7 +214,7 @@ int eg_ctx_create(const eg_config* cfg, eg_ctx** out) {
     ctx->own_stream = true;
   }
   if (c.blocks_per_cu < 0 || c.blocks_per_cu > 32 || c.dense_div < 0 || c.small_limit < 0 || c.small_limit > 65536 ||
-      c.partition < 0 || c.partition > 3 || c.top_seeding < 0 || c.top_seeding > 1 || c.seg_edges < -1 ||
+      c.partition < 0 || c.partition > 3 || c.top_seeding < 0 || c.top_seeding > 64 || c.seg_edges < -1 ||
       c.p1_filter < 0 || c.p1_filter > 1 || c.scc_schedule < 0 || c.scc_schedule > 1 || c.hub_cache < -1 || c.hub_cache > 64 ||
       c.relabel < 0 || c.relabel > 2 ||
       (c.seg_edges > 0 && c.seg_edges < 256)) {
@@ -259,6 +260,7 @@ static void game_free(eg_game* g) {
   if (g->h_blk) (void)hipHostFree(g->h_blk);
   if (g->h_stats) (void)hipHostFree(g->h_stats);
   if (g->seed_mem) (void)hipFree(g->seed_mem);
+  if (g->fbf_mem) (void)hipFree(g->fbf_mem);
   if (g->seg_mem) (void)hipFree(g->seg_mem);
   if (g->perm_mem) (void)hipFree(g->perm_mem);
   if (g->h_seed) (void)hipHostFree(g->h_seed);
@@ -825,6 +827,10 @@ static int solve_impl(eg_game* g, const eg_solve_opts* opts, int64_t* credits, e
   } else if (seeding) {
     if (!g->seed_mem) HIPCHK(hipMalloc(&g->seed_mem, eg::seed_bytes(g->n)));
     eg::bind_seed(g->sb, g->seed_mem, g->n);
+    if (ctx->cfg.top_seeding > 1) {
+      if (!g->fbf_mem) HIPCHK(hipMalloc(&g->fbf_mem, (size_t)g->n * (size_t)(g->vbits / 8)));
+      g->sb.fbf = g->fbf_mem;
+    }
   }
   uint64_t next_seed = 0, seeded = 0, seed_passes = 0;  // passes before the first round, then at doubling round counts
   for (;;) {
@@ -844,7 +850,7 @@ static int solve_impl(eg_game* g, const eg_solve_opts* opts, int64_t* credits, e
     }
     if (seeding && launched >= next_seed) {
       HIPCHK(hipEventRecord(g->ev[3], s));
-      HIPCHK(eg::launch_seed(dg, g->vbits, g->sb, r, seed_passes == 0 && !o.resume, s));
+      HIPCHK(eg::launch_seed(dg, g->vbits, g->sb, r, seed_passes == 0 && !o.resume, ctx->cfg.top_seeding, s));
       HIPCHK(hipEventRecord(g->ev[4], s));
       HIPCHK(hipMemcpyAsync(g->h_seed, g->sb.count, 4, hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));

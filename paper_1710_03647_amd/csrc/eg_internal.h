@@ -111,6 +111,7 @@ struct SeedBuf {
   uint8_t* forced;    // 1 for player-1 vertices and for player-0 vertices of out-degree 1
   uint8_t* oncyc;     // 1 for vertices on a cycle of the chosen edges
   long long* sum;     // per cycle (indexed by its smallest vertex): total weight
+  void* fbf;          // Bellman-Ford seeding passes: n values of the game's width (nullptr: one choice pass)
   uint32_t* count;    // 4 words: [0] vertices newly set to TOP, [1] long rows, [2] long predecessor
                       // lists, [3] medium rows
 };
@@ -143,7 +144,10 @@ size_t seed_bytes(int32_t n);
 void bind_seed(SeedBuf& sb, void* base, int32_t n);
 // f_zero: f is 0 everywhere (the pass before the first round of a solve that
 // does not resume), so the choice reads no values.
-hipError_t launch_seed(const DevGame& g, int vbits, const SeedBuf& sb, uint32_t r, bool f_zero, hipStream_t s);
+// passes > 1 (with sb.fbf set): that many Bellman-Ford passes over the forced
+// subgraph before the cycles are read off the last choice.
+hipError_t launch_seed(const DevGame& g, int vbits, const SeedBuf& sb, uint32_t r, bool f_zero, int passes,
+                       hipStream_t s);
 
 // Slot states of the batched iteration, and where a running slot's rounds run:
 // in the epochs (flag sweeps, one round per epoch) or in k_batch_small (lists,

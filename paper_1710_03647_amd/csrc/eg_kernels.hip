@@ -1773,6 +1773,28 @@ __device__ __forceinline__ void wave_seg_fold(bool& has, T& x, uint32_t slot, Be
   }
 }
 
+// Bellman-Ford seeding passes (sb.fbf set): the values iterated are those of
+// the game restricted to the forced subgraph, where player 1 picks among
+// forced successors and player 0 has no choice; from f (a measure below the
+// least fixpoint) they stay below it, since that restriction only drops
+// player-1 options.  The chosen edge's term under them raises v's value
+// (capped at the TOP encoding; a value above B proves TOP).
+template <typename V>
+__device__ __forceinline__ void seed_raise(const DevGame& g, const SeedBuf& sb, int32_t v, int32_t to, int32_t w) {
+  if (!sb.fbf || to < 0) return;
+  V* b = (V*)sb.fbf;
+  V tm = b[to] - (V)w;
+  tm = tm > V(0) ? tm : V(0);
+  if (tm > (V)g.top) tm = (V)g.top;
+  if (tm > b[v]) b[v] = tm;
+}
+
+// The values a choice pass reads: f, or the Bellman-Ford values.
+template <typename V>
+__device__ __forceinline__ const V* seed_values(const DevGame& g, const SeedBuf& sb) {
+  return sb.fbf ? (const V*)sb.fbf : (const V*)g.f;
+}
+
 // sigma1 for every player-1 vertex over its out-edges into the forced
 // subgraph, and the single edge of every player-0 vertex of out-degree 1.
 // The player-1 rows of up to SEED_FLAT edges of a tile of BLOCK vertices are
@@ -1794,7 +1816,7 @@ __global__ __launch_bounds__(BLOCK) void k_seed_choose(DevGame g, SeedBuf sb, in
   __shared__ unsigned long long kmax[BLOCK];
   __shared__ uint32_t kidx[BLOCK];
   __shared__ uint32_t wsum[BLOCK / WAVE];
-  const V* f = (const V*)g.f;
+  const V* f = seed_values<V>(g, sb);
   const uint32_t n = (uint32_t)g.n, tid = threadIdx.x, lane = lane_id();
   const uint32_t ntiles = (n + BLOCK - 1) / BLOCK;
   for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
@@ -1891,6 +1913,7 @@ __global__ __launch_bounds__(BLOCK) void k_seed_choose(DevGame g, SeedBuf sb, in
       sb.pl[0][v] = make_int2(to, (int32_t)v);
       sb.oncyc[v] = 0;
       sb.sum[v] = 0;
+      seed_raise<V>(g, sb, (int32_t)v, to, bw);
     }
     // the next tile rewrites epre, ebeg, kmax and kidx only after its scan's
     // barrier, which every thread reaches after its last read of them here
@@ -1903,7 +1926,7 @@ __global__ __launch_bounds__(BLOCK) void k_seed_choose(DevGame g, SeedBuf sb, in
 template <typename V>
 __global__ __launch_bounds__(BLOCK) void k_seed_choose_rows(DevGame g, SeedBuf sb, const int32_t* list,
                                                             const uint32_t* count, bool f_zero) {
-  const V* f = (const V*)g.f;
+  const V* f = seed_values<V>(g, sb);
   const uint32_t lane = lane_id();
   constexpr uint32_t NONE = 0xFFFFFFFFu;
   const uint32_t cnt = *count;
@@ -1963,6 +1986,7 @@ __global__ __launch_bounds__(BLOCK) void k_seed_choose_rows(DevGame g, SeedBuf s
       sb.succ[v] = best;
       sb.wgt[v] = bw;
       sb.pl[0][v].x = best;
+      seed_raise<V>(g, sb, v, best, bw);
     }
   }
 }
@@ -1984,7 +2008,7 @@ __global__ __launch_bounds__(BLOCK) void k_seed_choose_pieces(DevGame g, SeedBuf
                                                               const uint32_t* count, bool f_zero) {
   __shared__ unsigned long long s_key[BLOCK / WAVE];
   __shared__ uint32_t s_has[BLOCK / WAVE];
-  const V* f = (const V*)g.f;
+  const V* f = seed_values<V>(g, sb);
   constexpr uint32_t NONE = 0xFFFFFFFFu;
   const uint32_t tid = threadIdx.x, lane = lane_id(), wid = tid / WAVE;
   const uint32_t total = *count * SEED_PIECES;
@@ -2052,6 +2076,7 @@ __global__ __launch_bounds__(BLOCK) void k_seed_choose_pieces(DevGame g, SeedBuf
   }
 }
 
+template <typename V>
 __global__ void k_seed_choose_close(DevGame g, SeedBuf sb, const int32_t* list, const uint32_t* count) {
   const uint32_t cnt = *count;
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += gridDim.x * blockDim.x) {
@@ -2067,6 +2092,7 @@ __global__ void k_seed_choose_close(DevGame g, SeedBuf sb, const int32_t* list, 
     sb.wgt[v] = bw;
     sb.pl[0][v].x = to;
     sb.sum[v] = 0;
+    seed_raise<V>(g, sb, v, to, bw);
   }
 }
 
@@ -2111,7 +2137,8 @@ __global__ __launch_bounds__(BLOCK) void k_seed_apply(DevGame g, const SeedBuf s
     const uint32_t v = v0 + lane;
     bool set = false;
     uint32_t pb = 0, pe = 0;
-    if (v < n && sb.oncyc[v] && sb.sum[pl[v].y] < 0 && f[v] != top) {
+    const bool proven = v < n && ((sb.oncyc[v] && sb.sum[pl[v].y] < 0) || (sb.fbf && ((const V*)sb.fbf)[v] > (V)g.bound));
+    if (proven && f[v] != top) {
       f[v] = top;
       mine++;
       set = true;
@@ -2178,42 +2205,50 @@ void bind_seed(SeedBuf& sb, void* base, int32_t n) {
   sb.sum = (long long*)b;
   b += up(8 * nn);
   sb.count = (uint32_t*)b;
+  sb.fbf = nullptr;  // one choice pass unless the caller supplies the values of Bellman-Ford passes
 }
 
 // One seeding pass before round r; sb.count receives the number of vertices
 // set to TOP.  When it is nonzero the caller runs round r as a dense round
-// (ctrl[C_ANY0 + (r - 1) % 3] is set here).
-hipError_t launch_seed(const DevGame& g, int vbits, const SeedBuf& sb, uint32_t r, bool f_zero, hipStream_t s) {
+// (ctrl[C_ANY0 + (r - 1) % 3] is set here).  With passes > 1 (sb.fbf set) the
+// choice runs that many times as Bellman-Ford passes over the forced
+// subgraph from f, each on the values the last one raised, and the cycles
+// are read off the last choice.
+template <typename V>
+static void launch_choice(const DevGame& g, const SeedBuf& sb, int32_t* longs, int32_t* mids, bool f_zero, int grid,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_seed_choose<V>, dim3(grid), dim3(BLOCK), 0, s, g, sb, longs, mids, f_zero);
+  hipLaunchKernelGGL(k_seed_choose_rows<V>, dim3(SEED_MID_GRID), dim3(BLOCK), 0, s, g, sb, (const int32_t*)mids,
+                     (const uint32_t*)sb.count + 3, f_zero);
+  hipLaunchKernelGGL((k_seed_choose_pieces<V, 0>), dim3(SEED_LONG_GRID), dim3(BLOCK), 0, s, g, sb,
+                     (const int32_t*)longs, (const uint32_t*)sb.count + 1, f_zero);
+  hipLaunchKernelGGL((k_seed_choose_pieces<V, 1>), dim3(SEED_LONG_GRID), dim3(BLOCK), 0, s, g, sb,
+                     (const int32_t*)longs, (const uint32_t*)sb.count + 1, f_zero);
+  hipLaunchKernelGGL(k_seed_choose_close<V>, dim3(SEED_LONG_GRID / 4), dim3(BLOCK), 0, s, g, sb,
+                     (const int32_t*)longs, (const uint32_t*)sb.count + 1);
+}
+
+hipError_t launch_seed(const DevGame& g, int vbits, const SeedBuf& sb, uint32_t r, bool f_zero, int passes,
+                       hipStream_t s) {
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(((int64_t)g.n + BLOCK - 1) / BLOCK, 8192));
-  // count[0]: vertices set to TOP; count[1], count[2]: long rows and long
-  // predecessor lists handed to the block-per-row kernels, count[3]: rows
-  // handed to the wave-per-row kernel
-  hipError_t e = hipMemsetAsync(sb.count, 0, 16, s);
+  if (!sb.fbf) passes = 1;
+  hipError_t e = hipSuccess;
+  if (sb.fbf) e = hipMemcpyAsync(sb.fbf, g.f, (size_t)g.n * (size_t)(vbits / 8), hipMemcpyDeviceToDevice, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_seed_forced, dim3(grid), dim3(BLOCK), 0, s, g, sb);
   // the long-row list and the medium-row list live in the two halves of
   // pl[1] until the first doubling pass writes it
   int32_t* longs = (int32_t*)sb.pl[1];
   int32_t* mids = longs + g.n;
-  if (vbits == 32) {
-    hipLaunchKernelGGL(k_seed_choose<int32_t>, dim3(grid), dim3(BLOCK), 0, s, g, sb, longs, mids, f_zero);
-    hipLaunchKernelGGL(k_seed_choose_rows<int32_t>, dim3(SEED_MID_GRID), dim3(BLOCK), 0, s, g, sb,
-                       (const int32_t*)mids, (const uint32_t*)sb.count + 3, f_zero);
-    hipLaunchKernelGGL((k_seed_choose_pieces<int32_t, 0>), dim3(SEED_LONG_GRID), dim3(BLOCK), 0, s, g, sb,
-                       (const int32_t*)longs, (const uint32_t*)sb.count + 1, f_zero);
-    hipLaunchKernelGGL((k_seed_choose_pieces<int32_t, 1>), dim3(SEED_LONG_GRID), dim3(BLOCK), 0, s, g, sb,
-                       (const int32_t*)longs, (const uint32_t*)sb.count + 1, f_zero);
-  } else {
-    hipLaunchKernelGGL(k_seed_choose<int64_t>, dim3(grid), dim3(BLOCK), 0, s, g, sb, longs, mids, f_zero);
-    hipLaunchKernelGGL(k_seed_choose_rows<int64_t>, dim3(SEED_MID_GRID), dim3(BLOCK), 0, s, g, sb,
-                       (const int32_t*)mids, (const uint32_t*)sb.count + 3, f_zero);
-    hipLaunchKernelGGL((k_seed_choose_pieces<int64_t, 0>), dim3(SEED_LONG_GRID), dim3(BLOCK), 0, s, g, sb,
-                       (const int32_t*)longs, (const uint32_t*)sb.count + 1, f_zero);
-    hipLaunchKernelGGL((k_seed_choose_pieces<int64_t, 1>), dim3(SEED_LONG_GRID), dim3(BLOCK), 0, s, g, sb,
-                       (const int32_t*)longs, (const uint32_t*)sb.count + 1, f_zero);
+  for (int p = 0; p < passes; p++) {
+    // count[0]: vertices set to TOP; count[1], count[2]: long rows and long
+    // predecessor lists handed to the block-per-piece and group kernels,
+    // count[3]: rows handed to the wave-per-row kernel
+    e = hipMemsetAsync(sb.count, 0, 16, s);
+    if (e != hipSuccess) return e;
+    if (vbits == 32) launch_choice<int32_t>(g, sb, longs, mids, f_zero && p == 0, grid, s);
+    else launch_choice<int64_t>(g, sb, longs, mids, f_zero && p == 0, grid, s);
   }
-  hipLaunchKernelGGL(k_seed_choose_close, dim3(SEED_LONG_GRID / 4), dim3(BLOCK), 0, s, g, sb, (const int32_t*)longs,
-                     (const uint32_t*)sb.count + 1);
   int cur = 0;
   for (int64_t span = 1; span <= 2 * (int64_t)g.n; span *= 2, cur ^= 1)
     hipLaunchKernelGGL(k_seed_jump, dim3(grid), dim3(BLOCK), 0, s, g.n, (const int2*)sb.pl[cur], sb.pl[cur ^ 1]);

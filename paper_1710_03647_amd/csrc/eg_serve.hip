@@ -325,7 +325,7 @@ int Server::admit_one(Ticket* t) {
     // part of the range, free once the upload (side stream) has completed
     SeedBuf sb{};
     bind_seed(sb, staging, t->n);
-    e = launch_seed(dg, vbits, sb, 1, true, main);  // f was just set to 0
+    e = launch_seed(dg, vbits, sb, 1, true, 1, main);  // f was just set to 0; one choice pass
   }
   // publish: descriptor, zero counters, mode and first round, then the state
   h_games[slot] = dg;

@@ -151,3 +151,48 @@ def test_seeding_candidate_order_in_every_row_path(sctx, oracle_mod, deg, mode):
     f, st = seeded_solve(sctx, game)
     pins.expect_equal(f, oracle_mod.solve(game).f, game.name)
     assert st["seeded"] == (2 if mode == "tie" else 1), (game.name, st["seeded"])
+
+
+def off_choice_cycle_game(fillers=47):
+    """Player-1 vertex 0 has a larger first-pass term towards 1 (a player-1
+    vertex with a positive self-loop) than towards 2, and 0 -> 2 -> 0 sums to
+    -2: player 1 wins from 0 and 2, but the first choice pass follows 0 -> 1
+    and sees no negative cycle.  Isolated fillers raise B = (n - 1) W, so
+    the plain climb is long."""
+    n = 3 + fillers
+    edges = [(0, 1, -10), (0, 2, -1), (1, 1, 100), (2, 0, -1)]
+    edges += [(v, v, 0) for v in range(3, n)]
+    owner = [1, 1, 1] + [0] * fillers
+    return synth.make_game(n, edges, owner, W=100, name="off-choice-cycle")
+
+
+def test_bellman_ford_seeding_finds_a_cycle_off_the_first_choice(oracle_mod):
+    """top_seeding = k > 1 runs k Bellman-Ford passes over the forced subgraph
+    before reading the cycles off the choice: the pass values make 0 -> 2
+    the better edge, so the first seeding pass proves 0 and 2 TOP (Lemma 1),
+    where one choice pass proves nothing until later passes at doubling
+    round counts."""
+    game = off_choice_cycle_game()
+    want = oracle_mod.solve(game).f
+    assert want[0] == TOP and want[2] == TOP and want[1] == 0
+    with eg.Context(0, top_seeding=1) as c1:
+        f1, st1 = seeded_solve(c1, game)
+    with eg.Context(0, top_seeding=8) as c8:
+        f8, st8 = seeded_solve(c8, game)
+    pins.expect_equal(f1, want, "one choice pass")
+    pins.expect_equal(f8, want, "8 Bellman-Ford passes")
+    assert st8["seeded"] >= 2 and st8["seed_passes"] == 1, st8
+    assert st8["rounds"] * 8 < st1["rounds"], (st8["rounds"], st1["rounds"])
+
+
+def test_bellman_ford_seeding_brute_force():
+    with eg.Context(0, top_seeding=4) as ctx:
+        pins.pin_brute(lambda g: seeded_solve(ctx, g)[0], count=200, seed0=91_000)
+
+
+@pytest.mark.parametrize("name,make", SEEDED, ids=[s[0] for s in SEEDED])
+def test_bellman_ford_seeding_matches_oracle(oracle_mod, name, make):
+    game = make()
+    with eg.Context(0, top_seeding=6) as ctx:
+        f, st = seeded_solve(ctx, game)
+    pins.expect_equal(f, oracle_mod.solve(game).f, f"{name} (6 Bellman-Ford passes)")
