@@ -785,14 +785,43 @@ static int solve_impl(eg_game* g, const eg_solve_opts* opts, int64_t* credits, e
   g->dg.cur_level = 0;
   const uint64_t dense_at = std::max<uint64_t>(1, (uint64_t)g->n / (ctx->cfg.dense_div ? ctx->cfg.dense_div : 32));
   const uint64_t small_limit = ctx->cfg.small_limit ? (uint64_t)ctx->cfg.small_limit : eg::SMALL_LIMIT;
+  const bool seeding = fixed_sb || ctx->cfg.top_seeding != 0;
+  if (fixed_sb) {
+    g->sb = *fixed_sb;
+  } else if (seeding) {
+    if (!g->seed_mem) HIPCHK(hipMalloc(&g->seed_mem, eg::seed_bytes(g->n)));
+    eg::bind_seed(g->sb, g->seed_mem, g->n);
+    if (ctx->cfg.top_seeding > 1) {
+      if (!g->fbf_mem) HIPCHK(hipMalloc(&g->fbf_mem, (size_t)g->n * (size_t)(g->vbits / 8)));
+      g->sb.fbf = g->fbf_mem;
+    }
+  }
+  uint64_t next_seed = 0, seeded = 0, seed_passes = 0;  // passes before the first round, then at doubling round counts
+  double t_seed = 0;                                    // device time of the seeding passes
   HIPCHK(hipMemsetAsync(dg.ctrl, 0, 4 * eg::C_WORDS, s));
   HIPCHK(hipMemsetAsync(dg.slots, 0, 8 * eg::S_WORDS * (size_t)grid, s));
   HIPCHK(hipEventRecord(g->ev[0], s));
   HIPCHK(eg::launch_init(dg, g->vbits, o.resume ? 1 : 0, grid, s));
   // component schedule: level 0 replaces the initial active set
   if (scc) HIPCHK(eg::launch_level_activate(dg, g->scc.lev, 0, 1, grid, s));
+  // the first seeding pass needs no decision of the host: it goes with init,
+  // and one synchronization reads both
+  if (seeding) {
+    HIPCHK(hipEventRecord(g->ev[3], s));
+    HIPCHK(eg::launch_seed(dg, g->vbits, g->sb, 1, !o.resume, ctx->cfg.top_seeding, s));
+    HIPCHK(hipEventRecord(g->ev[4], s));
+    HIPCHK(hipMemcpyAsync(g->h_seed, g->sb.count, 4, hipMemcpyDeviceToHost, s));
+  }
   HIPCHK(hipMemcpyAsync(g->h_blk, dg.blk_chg, 4 * (size_t)grid, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
+  if (seeding) {
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, g->ev[3], g->ev[4]);
+    t_seed += ms * 1e-3;
+    seed_passes = 1;
+    next_seed = 64;
+    seeded += *g->h_seed;
+  }
   uint64_t active = 0;
   for (int b = 0; b < grid; b++) active += g->h_blk[b];
   const int32_t nlevels = scc ? (int32_t)g->scc_info.levels : 1;
@@ -815,24 +844,13 @@ static int solve_impl(eg_game* g, const eg_solve_opts* opts, int64_t* credits, e
   if (mode == DENSE && !scc && (dg.nparts == 1 || dg.slice_major) &&
       (double)active * g->avg_indeg >= (double)g->n)
     mode = ALL;
+  // the predecessors of the first pass's TOP vertices are flagged for round 1
+  if (seeding && *g->h_seed && mode != ALL) mode = DENSE;
   if (active && mode != DENSE && mode != ALL) HIPCHK(eg::launch_compact(dg, 1, grid, s));
   wide = 2 * active >= (uint64_t)g->n;
   uint32_t batch = 2;
   double t_kernels = 0;  // device time of the round kernels (back to back within a batch)
-  double t_seed = 0;     // device time of the seeding passes
   uint64_t dense_rounds = 0, all_rounds = 0, all_streak = 0;
-  const bool seeding = fixed_sb || ctx->cfg.top_seeding != 0;
-  if (fixed_sb) {
-    g->sb = *fixed_sb;
-  } else if (seeding) {
-    if (!g->seed_mem) HIPCHK(hipMalloc(&g->seed_mem, eg::seed_bytes(g->n)));
-    eg::bind_seed(g->sb, g->seed_mem, g->n);
-    if (ctx->cfg.top_seeding > 1) {
-      if (!g->fbf_mem) HIPCHK(hipMalloc(&g->fbf_mem, (size_t)g->n * (size_t)(g->vbits / 8)));
-      g->sb.fbf = g->fbf_mem;
-    }
-  }
-  uint64_t next_seed = 0, seeded = 0, seed_passes = 0;  // passes before the first round, then at doubling round counts
   for (;;) {
     if (!active) {
       // the active set is empty: the fixpoint, or with the component
@@ -873,7 +891,9 @@ static int solve_impl(eg_game* g, const eg_solve_opts* opts, int64_t* credits, e
     // All-vertex rounds each cost a full lift, and a batch may overshoot the
     // end of the phase: one at a time at first, then batches of half the
     // phase so far (long phases, as on the uniform game, pay few syncs).
-    else if (mode == ALL) allowed = std::min<uint64_t>(64, std::max<uint64_t>(1, all_streak / 2));
+    // (the first two rounds of a solve that starts with them are both of
+    // this kind: round 1 raises every initially active vertex)
+    else if (mode == ALL) allowed = launched == 0 ? 2 : std::min<uint64_t>(64, std::max<uint64_t>(1, all_streak / 2));
     else allowed = batch;
     if (max_rounds) allowed = std::min<uint64_t>(allowed, max_rounds - launched);
     HIPCHK(hipEventRecord(g->ev[3], s));
