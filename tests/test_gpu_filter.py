@@ -44,8 +44,8 @@ GAMES = [
 # launch shapes that force each representation of the active set
 SHAPES = [
     ("default", {}),
-    ("lists", {"dense_div": 1 << 20, "small_limit": 1}),      # list rounds almost throughout
-    ("flags", {"dense_div": 1, "small_limit": 1}),            # flag sweeps throughout
+    ("flags", {"dense_div": 1 << 20, "small_limit": 1}),      # flag sweeps (or all-vertex rounds) throughout
+    ("lists", {"dense_div": 1, "small_limit": 1}),            # list rounds almost throughout
     ("small", {"small_limit": 65536}),                        # the single-block mode takes most rounds
     ("uncut", {"seg_edges": -1, "relabel": 1, "blocks_per_cu": 2}),
     ("cut-256", {"seg_edges": 256}),                          # many cut tiles
@@ -65,13 +65,16 @@ def test_filter_matches_oracle(oracle_mod, name, make, shape):
 
 def test_filter_cuts_lifts_and_keeps_credits(oracle_mod):
     """Same credits with and without the filter; the filter leaves predecessors
-    out and so lifts fewer vertices."""
+    out and so lifts fewer vertices.  List rounds throughout (all-vertex
+    rounds scan no predecessors, so the default shape may leave nothing to
+    filter)."""
     game = synth.gen_uniform(1 << 14, 16, 1000, 2)
     want = oracle_mod.solve(game).f
-    with eg.Context(0) as ctx:
+    lists = {"dense_div": 1, "small_limit": 1}
+    with eg.Context(0, **lists) as ctx:
         with ctx.create(game) as g:
             f0, st0, _ = g.solve()
-    f1, st1 = solve(game)
+    f1, st1 = solve(game, **lists)
     pins.expect_equal(f0, want, "unfiltered")
     pins.expect_equal(f1, want, "filtered")
     assert st1["filtered_preds"] > 0

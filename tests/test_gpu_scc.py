@@ -114,8 +114,8 @@ SHAPES = [
     ("default", {}),
     ("seeded", {"top_seeding": 1}),
     ("filter", {"p1_filter": 1}),
-    ("lists", {"dense_div": 1 << 20, "small_limit": 1}),
-    ("flags", {"dense_div": 1, "small_limit": 1}),
+    ("flags", {"dense_div": 1 << 20, "small_limit": 1}),  # flag sweeps (dense_at = 1)
+    ("lists", {"dense_div": 1, "small_limit": 1}),  # list rounds (dense_at = n)
     ("small", {"small_limit": 65536}),
 ]
 
