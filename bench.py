@@ -22,9 +22,10 @@ Also reported (each leg once, after the timed steps, each under a time cap):
   step_parts    where a step's time goes: seeding passes, round kernels, the
                 rest (init, host sync, result copy);
   rmat_lift     full-frontier lift rounds of the same game from its least
-                fixpoint (every vertex lifted, none changes: the lift alone),
-                against the HBM roofline, in place (cut tiles), per-XCD sliced
-                and slice-major; and player 0's strategy kernel;
+                fixpoint (every vertex lifted, none changes: the lift alone;
+                all-vertex rounds where the shape allows them), against the
+                HBM roofline, in place (cut tiles), per-XCD sliced and
+                slice-major; and player 0's strategy kernel;
   work_options  the same seeded solve with the player-1 frontier filter and
                 with the component schedule: rounds, lifts, time, credits;
   uniform       the uniform random game (n = 2^20, out-degree 16, weights in
